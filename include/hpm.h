@@ -1,0 +1,224 @@
+/*
+ * hpm.h -- edge-centric subgraph matching on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libhpm.so.  The library finds every embedding of a small labelled
+ * pattern digraph in a large labelled target digraph, for induced subgraph
+ * isomorphism or for monomorphism (HiPerMotif, arXiv 2507.04130):
+ *   - the pattern is reordered by degree (Sec. III-A, Alg. 1, "Structural
+ *     Reordering");
+ *   - every target arc is scanned as a candidate image of pattern arc (0,1)
+ *     and filtered by the vertex validator (Sec. III-B, Alg. 2) and the edge
+ *     validator's attribute, reverse-arc and degree checks (Sec. III-B, Alg. 3);
+ *   - the survivors become depth-2 partial mappings (state injection,
+ *     Sec. III-C, Alg. 4) and are extended one pattern vertex at a time under
+ *     the feasibility rules of the problem definition (Sec. II-A, Eq. (1)-(3)).
+ *
+ * All functions return an int status: HPM_OK (0) or a negative HPM_E_* code.
+ * On error, hpm_last_error() returns a message for the calling thread.  No
+ * C++ exception ever crosses this boundary.
+ *
+ * Graph and pattern conventions (Sec. II-A; storage after Sec. III-D, "double
+ * index" CSR with contiguous attribute arrays):
+ *   - vertices are 0..n-1; arcs are ordered pairs (u,v), u != v, no repeats;
+ *   - the out-CSR lists, for each u, the heads of its out-arcs in strictly
+ *     ascending order; arc id e is the position of the arc in that array;
+ *   - the in-CSR is its transpose (for each v the tails of its in-arcs, strictly
+ *     ascending);
+ *   - attributes are int32 columns: vertex columns indexed by vertex, arc
+ *     columns indexed by out-CSR arc id.
+ */
+#ifndef HPM_H_
+#define HPM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPM_ABI_VERSION 1
+#define HPM_MAX_K 16   /* largest pattern, in vertices            */
+#define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
+
+enum {
+  HPM_OK = 0,
+  HPM_E_ARG = -1,         /* NULL or out-of-range argument                         */
+  HPM_E_GRAPH = -2,       /* malformed target graph                                */
+  HPM_E_PATTERN = -3,     /* malformed pattern                                     */
+  HPM_E_NOMEM = -4,       /* device allocation failed or budget below one chunk    */
+  HPM_E_TRUNCATED = -5,   /* more matches than the mapping buffer holds            */
+  HPM_E_OVERFLOW = -6,    /* match count does not fit in uint64                    */
+  HPM_E_DEVICE = -7,      /* HIP runtime error                                     */
+  HPM_E_UNSUPPORTED = -8, /* valid input beyond the library's limits (n, m >= 2^31) */
+  HPM_E_INTERNAL = -9     /* unexpected internal failure                           */
+};
+
+typedef enum { HPM_ISO = 0, HPM_MONO = 1 } hpm_mode;
+
+/* Predicate on one int32 attribute.  HPM_EQ is the label equality of
+ * Sec. II-A, Eq. (2)-(3); HPM_GE is a threshold (value >= val); HPM_ANY leaves
+ * the column unconstrained.  A vertex or arc satisfies its predicates when
+ * every column does. */
+typedef enum { HPM_ANY = 0, HPM_EQ = 1, HPM_GE = 2 } hpm_op;
+
+typedef struct hpm_graph hpm_graph; /* opaque, device-resident, immutable */
+
+/*
+ * hpm_graph_create -- copy a target graph into library-owned device memory.
+ *
+ * n          vertices, 0 <= n < 2^31 - 1.
+ * m          arcs, 0 <= m < 2^31.
+ * out_off    host int64[n+1]: out_off[0] = 0, non-decreasing, out_off[n] = m.
+ * out_nbrs   host int32[m]: heads, each row strictly ascending, no u in row u.
+ * in_off     host int64[n+1], in_nbrs host int32[m]: the transpose.
+ * n_vcols    0..HPM_MAX_COLS vertex columns; vcols[c] is a host int32[n].
+ * n_ecols    0..HPM_MAX_COLS arc columns; ecols[c] is a host int32[m] in
+ *            out-CSR arc order.
+ * stream     hipStream_t (NULL = default stream) used for uploads and checks;
+ *            the call synchronises it before returning.
+ * *out       receives the handle; destroy it with hpm_graph_destroy.
+ *
+ * All inputs are host pointers and are copied; the caller may free them on
+ * return.  The library derives on the device the arc tail array (the paper's
+ * edge-to-source index), the in-to-out arc id map and the degrees, and checks
+ * on the device that rows are strictly ascending, ids are in range, there are
+ * no self-loops and the in-CSR is exactly the transpose of the out-CSR.
+ * Errors: HPM_E_ARG (NULL pointers, column counts out of range),
+ * HPM_E_UNSUPPORTED (n or m too large), HPM_E_GRAPH (any structural check
+ * fails; nothing is kept), HPM_E_NOMEM, HPM_E_DEVICE.
+ */
+int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_off,
+                     const int32_t* out_nbrs, const int64_t* in_off, const int32_t* in_nbrs,
+                     int32_t n_vcols, const int32_t* const* vcols, int32_t n_ecols,
+                     const int32_t* const* ecols, void* stream);
+
+/* Release a graph and all its device memory.  No match may be in flight on it.
+ * NULL is accepted and ignored. */
+int hpm_graph_destroy(hpm_graph* g);
+
+/* Sizes of a graph and the device bytes it holds (any output may be NULL). */
+int hpm_graph_info(const hpm_graph* g, int32_t* n, int64_t* m, uint64_t* device_bytes);
+
+/*
+ * A pattern (query) digraph on vertices 0..k-1 (Sec. II-A).
+ * k        2..HPM_MAX_K.
+ * n_arcs   1..k*(k-1); arcs src[i] -> dst[i], no self-loops, no repeats; the
+ *          pattern must be weakly connected.
+ * vop/vval int32[k][n_vcols] (row-major): predicate of vertex a on column c is
+ *          (vop[a*n_vcols+c], vval[a*n_vcols+c]); NULL means all HPM_ANY.
+ * eop/eval int32[n_arcs][n_ecols]: predicate of arc i on column c; NULL means
+ *          all HPM_ANY.  A reciprocal pair (a,b),(b,a) has two arcs with their
+ *          own predicates.
+ * n_vcols/n_ecols must equal the graph's.  All pointers are host pointers.
+ */
+typedef struct {
+  int32_t k, n_arcs;
+  const int32_t *src, *dst;
+  const int32_t *vop, *vval;
+  const int32_t *eop, *eval;
+} hpm_pattern;
+
+/* Flags for hpm_match_opts.flags. */
+#define HPM_F_NO_REORDER 0x1u /* keep pattern order (vertex 0 first, then the   \
+                                 smallest-id vertex adjacent to those placed)   \
+                                 instead of the degree-based reordering.  Same   \
+                                 result, used to check that reordering does not  \
+                                 change it. */
+#define HPM_F_TIMING 0x2u     /* record per-phase device times (hpm_last_stats) */
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(hpm_match_opts)                         */
+  uint32_t flags;            /* HPM_F_*                                        */
+  uint64_t hbm_budget_bytes; /* scratch limit; 0 = 25% of free device memory   */
+} hpm_match_opts;
+
+/*
+ * hpm_match -- count (and optionally list) all embeddings of p in g.
+ *
+ * mode      HPM_ISO (induced: arcs and non-arcs both preserved, Eq. (1) "<=>")
+ *           or HPM_MONO (arcs preserved, Eq. (1) "=>").
+ * stream    hipStream_t (NULL = default) on which all work is enqueued; the call
+ *           synchronises it before returning.
+ * opts      NULL for defaults.
+ * count     required host uint64*: number of embeddings.  Embeddings are
+ *           injective maps, so automorphic images count separately.
+ * mappings  NULL, or a DEVICE int32 buffer of cap rows of k entries.  Row r holds
+ *           f(0), ..., f(k-1) in the caller's original pattern-vertex ids.  Row
+ *           order is unspecified.
+ * cap       rows available in mappings (ignored when mappings is NULL).
+ *
+ * The scratch space (partial-mapping frontiers) is bounded by
+ * opts->hbm_budget_bytes; the frontier is expanded in chunks that fit it, so the
+ * result never depends on the budget.  Several calls may run concurrently on
+ * different streams with the same graph.
+ * Errors: HPM_E_ARG, HPM_E_PATTERN (invalid pattern or column-count mismatch),
+ * HPM_E_NOMEM (budget below the minimum chunk, or allocation failure),
+ * HPM_E_TRUNCATED (*count > cap: *count is valid, the first cap rows written are
+ * valid embeddings but which ones is unspecified), HPM_E_OVERFLOW, HPM_E_DEVICE.
+ */
+int hpm_match(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* stream,
+              const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap);
+
+/*
+ * hpm_plan_order -- the matching order hpm_match would use (host only, no device).
+ *
+ * order[pos] receives the original pattern vertex placed at position pos
+ * (int32[k]).  Positions 0 and 1 are the arc the target scan starts from.
+ * Implements the structural reordering of Sec. III-A (Alg. 1): rank
+ * sigma(v) = (in+out degree, out degree), first the best-ranked vertex, then
+ * repeatedly the best-ranked unplaced out-neighbour of the last placed vertex;
+ * when there is none, the best-ranked unplaced vertex adjacent to any placed
+ * vertex (the paper takes any unplaced vertex; restricting to adjacent ones
+ * keeps every position after the first connected to an earlier one).  Ties
+ * go to the smaller original id.  flags: 0 or HPM_F_NO_REORDER.
+ * n_vcols/n_ecols: the column counts the predicates are laid out for.
+ * Errors: HPM_E_ARG, HPM_E_PATTERN.
+ */
+int hpm_plan_order(const hpm_pattern* p, int32_t n_vcols, int32_t n_ecols, uint32_t flags,
+                   int32_t* order);
+
+/* Kernel families, indexing hpm_match_stats.kernel_ms / kernel_launches. */
+enum {
+  HPM_K_VERTEX_VALIDATOR = 0, /* flags for positions 0 and 1 (Alg. 2)               */
+  HPM_K_EDGE_SCAN = 1,        /* every arc vs pattern arc (0,1), compaction (Alg. 3) */
+  HPM_K_ROW_PIVOT = 2,        /* candidate source and list length per partial map    */
+  HPM_K_PREFIX_SUM = 3,       /* exclusive sums of the list lengths                  */
+  HPM_K_EXPAND = 4,           /* extend partial mappings by one vertex               */
+  HPM_K_LAST_LEVEL = 5,       /* final vertex: count (and write mappings)            */
+  HPM_K_REDUCE = 6,           /* per-block counts -> total                           */
+  HPM_K_NUM = 7
+};
+
+/* Per-call statistics of the calling thread's most recent successful hpm_match.
+ * kernel_ms is filled only when HPM_F_TIMING was set (device time from HIP
+ * events recorded around every launch on the caller's stream), else 0. */
+typedef struct {
+  uint64_t struct_size;          /* sizeof(hpm_match_stats)                           */
+  uint64_t count;                /* embeddings                                        */
+  uint64_t arcs_scanned;         /* target arcs tested as images of pattern arc (0,1)  */
+  uint64_t survivors;            /* depth-2 partial mappings after the validators     */
+  uint64_t rows[HPM_MAX_K + 1];  /* partial mappings materialised per depth           */
+  uint64_t work[HPM_MAX_K + 1];  /* candidates examined to fill position d            */
+  uint64_t chunks;               /* frontier chunks processed                         */
+  uint64_t scratch_bytes;        /* device scratch held by the call                   */
+  uint64_t kernel_launches[HPM_K_NUM];
+  double kernel_ms[HPM_K_NUM];
+  double ms_total;               /* host wall time of the call                        */
+} hpm_match_stats;
+
+int hpm_last_stats(hpm_match_stats* out);
+
+/* Static description of a status code, and the calling thread's last error
+ * message ("" if none).  The returned strings stay valid until the thread's
+ * next hpm_* call. */
+const char* hpm_status_string(int status);
+const char* hpm_last_error(void);
+
+/* ABI version this library was built with (HPM_ABI_VERSION). */
+int hpm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPM_H_ */

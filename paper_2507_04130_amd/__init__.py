@@ -1,0 +1,8 @@
+"""Edge-centric subgraph matching (HiPerMotif, arXiv 2507.04130) on AMD MI355X.
+
+The matcher is libhpm.so (HIP kernels for gfx950 behind the C ABI of
+include/hpm.h); this package holds its sources (csrc/), the build script and a
+thin ctypes binding.
+"""
+from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_REORDER, F_TIMING, Graph, HpmError,  # noqa: F401
+                  abi_version, last_stats, load, match, plan_order, status_string)

@@ -1,0 +1,104 @@
+// hpm_internal.h -- types shared by the HIP kernels and the host runtime of libhpm.
+//
+// Nothing here is part of the public ABI (include/hpm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpm {
+
+constexpr int kMaxK = 16;
+constexpr int kMaxCols = 4;
+constexpr int kBlock = 256;           // threads per block (4 wave64s)
+constexpr int kWaves = kBlock / 64;
+constexpr int kScanItems = 16;        // arcs per thread per tile in the arc scan
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kExpandItems = 4;       // candidates per thread per tile in the extension
+constexpr int kExpandTile = kBlock * kExpandItems;
+constexpr int kPivotItems = 4;        // rows per thread in the pivot/length pass
+constexpr int kPivotTile = kBlock * kPivotItems;
+
+// Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.
+struct DevGraph {
+  int32_t n;
+  int32_t m;
+  const int32_t* out_off;   // [n+1]
+  const int32_t* out_nbrs;  // [m]   heads, rows ascending
+  const int32_t* in_off;    // [n+1]
+  const int32_t* in_nbrs;   // [m]   tails, rows ascending
+  const int32_t* src;       // [m]   tail of out-CSR arc e (edge-to-source index)
+  const int32_t* in_eid;    // [m]   out-CSR arc id of in-CSR position j
+  int32_t n_vcols, n_ecols;
+  const int32_t* vcol[kMaxCols];  // [n] each
+  const int32_t* ecol[kMaxCols];  // [m] each, out-CSR order
+};
+
+// Matching plan in "position" space: position p holds original pattern vertex
+// orig[p]; positions are filled in increasing order.  Predicates are stored as
+// inclusive int32 ranges per column (ANY = full range, EQ v = [v,v],
+// GE v = [v, INT32_MAX]); a mask bit says which columns need reading at all.
+struct DevPlan {
+  int32_t k;
+  int32_t mode;          // 0 induced isomorphism, 1 monomorphism
+  int32_t mve_forward;   // 1: scanned arc x->y binds pos0=x, pos1=y; 0: pos1=x, pos0=y
+  int32_t rev_rule;      // reverse of the scanned arc: 0 ignore, 1 required (+pred 1->0), 2 forbidden
+  int32_t pin[kMaxK];    // pattern in-degree per position
+  int32_t pout[kMaxK];   // pattern out-degree per position
+  uint32_t vmask[kMaxK];
+  int32_t vlo[kMaxK][kMaxCols];
+  int32_t vhi[kMaxK][kMaxCols];
+  uint32_t fwd[kMaxK];   // bit b of fwd[a]: arc (pos b -> pos a) in the pattern, b < a
+  uint32_t bwd[kMaxK];   // bit b of bwd[a]: arc (pos a -> pos b) in the pattern, b < a
+  uint32_t amask[kMaxK][kMaxK];  // columns constrained on arc (p -> q)
+  int32_t alo[kMaxK][kMaxK][kMaxCols];
+  int32_t ahi[kMaxK][kMaxK][kMaxCols];
+  int32_t orig[kMaxK];
+};
+
+// Error bits raised by the graph-checking kernels.
+enum : uint32_t {
+  kErrRange = 1u,        // neighbour id outside [0, n)
+  kErrSelfLoop = 2u,
+  kErrUnsorted = 4u,     // row not strictly ascending (covers repeats)
+  kErrTranspose = 8u,    // in-CSR is not the transpose of the out-CSR
+};
+
+// ---- launchers (hpm_kernels.hip) -------------------------------------------------
+// Every launcher enqueues on `stream` and returns the launch status.
+
+hipError_t launch_derive_rows(const int32_t* off, int32_t n, int32_t m, int32_t* row_of,
+                              hipStream_t stream);
+hipError_t launch_check_rows(const int32_t* off, const int32_t* nbrs, const int32_t* row_of,
+                             int32_t n, int32_t m, uint32_t* err, hipStream_t stream);
+hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
+                                const int32_t* in_row, const int32_t* out_off,
+                                const int32_t* out_nbrs, int32_t n, int32_t m, int32_t* in_eid,
+                                uint32_t* err, hipStream_t stream);
+
+hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint8_t* vflag,
+                                   hipStream_t stream);
+// out_mode: 0 write depth-2 rows [.][2] in position order; 1 count only;
+// 2 write final rows [.][2] in original pattern order (two-vertex patterns).
+hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint8_t* vflag,
+                            int32_t e_begin, int32_t e_end, int out_mode, int32_t* out,
+                            unsigned long long* cursor, unsigned long long out_cap,
+                            int grid, hipStream_t stream);
+// Pivot choice and candidate-list length of every row at depth d; writes piv[r],
+// len into off[0..r) and per-block sums into bsum[ceil(r / kPivotTile)].
+hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
+                            const int32_t* rows, int32_t r, int32_t* piv, int64_t* off,
+                            int64_t* bsum, hipStream_t stream);
+// Turns the lengths in off[0..r) into exclusive prefix sums; off[r] = total.
+hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream_t stream);
+// out_mode: 0 write depth d+1 rows; 1 count only; 2 count and write final rows.
+hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, int32_t d, const int32_t* rows,
+                         const int64_t* off, const int32_t* piv, int32_t r, int64_t w_begin,
+                         int64_t w_end, int out_mode, int32_t* out, unsigned long long* cursor,
+                         unsigned long long out_cap, unsigned long long* partials, int grid,
+                         hipStream_t stream);
+// total[0] += sum(partials[0..nparts)); overflow[0] |= 1 on uint64 wrap.
+hipError_t launch_reduce_counts(const unsigned long long* partials, int32_t nparts,
+                                unsigned long long* total, uint32_t* overflow, hipStream_t stream);
+
+}  // namespace hpm

@@ -1,0 +1,826 @@
+// hpm_runtime.hip -- host side of libhpm: C ABI, graph store, pattern plan and
+// the chunked depth scheduler.  All matching arithmetic runs in the kernels of
+// hpm_kernels.hip; this file validates inputs, orders the pattern, sizes
+// scratch memory and sequences launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hpm.h"
+#include "hpm_internal.h"
+
+namespace {
+
+using hpm::DevGraph;
+using hpm::DevPlan;
+using hpm::kMaxCols;
+using hpm::kMaxK;
+
+thread_local std::string t_error;
+thread_local hpm_match_stats t_stats;
+
+struct Failure {
+  int status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string& msg) { throw Failure{status, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  const int st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HPM_E_NOMEM
+                                                                             : HPM_E_DEVICE;
+  fail(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    t_error.clear();
+    return f();
+  } catch (const Failure& e) {
+    t_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    t_error = "host allocation failed";
+    return HPM_E_NOMEM;
+  } catch (const std::exception& e) {
+    t_error = e.what();
+    return HPM_E_INTERNAL;
+  } catch (...) {
+    t_error = "unknown internal error";
+    return HPM_E_INTERNAL;
+  }
+}
+
+// Owned device allocation that can grow.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // Make room for at least `want` bytes; contents are not preserved.
+  void ensure(size_t want, hipStream_t stream) {
+    if (want <= bytes) return;
+    if (p) {
+      hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+      release();
+    }
+    hip_check(hipMalloc(&p, want), "hipMalloc");
+    bytes = want;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Per-call scratch.  Pooled per graph so that concurrent calls (different
+// streams) never share one, and repeated calls reuse allocations.
+struct Workspace {
+  DevBuf plan, vflag, counters, partials, rows2;
+  DevBuf off[kMaxK], piv[kMaxK], bsum[kMaxK], rows[kMaxK];
+  unsigned long long* host = nullptr;  // pinned readback slots
+  DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
+  std::vector<hipEvent_t> events;
+  ~Workspace() {
+    if (host) (void)hipHostFree(host);
+    if (host_plan) (void)hipHostFree(host_plan);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+  size_t held() const {
+    size_t s = plan.bytes + vflag.bytes + counters.bytes + partials.bytes + rows2.bytes;
+    for (int d = 0; d < kMaxK; ++d) s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes;
+    return s;
+  }
+  void release_all() {
+    plan.release(); vflag.release(); counters.release(); partials.release(); rows2.release();
+    for (int d = 0; d < kMaxK; ++d) { off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release(); }
+  }
+};
+
+}  // namespace
+
+struct hpm_graph {
+  int device = 0;
+  int num_cus = 256;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t n_vcols = 0, n_ecols = 0;
+  DevBuf out_off, out_nbrs, in_off, in_nbrs, src, in_eid;
+  DevBuf vcols[kMaxCols], ecols[kMaxCols];
+  std::mutex mu;
+  std::vector<Workspace*> pool;
+
+  ~hpm_graph() {
+    for (Workspace* w : pool) delete w;
+  }
+  uint64_t bytes() const {
+    uint64_t s = out_off.bytes + out_nbrs.bytes + in_off.bytes + in_nbrs.bytes + src.bytes +
+                 in_eid.bytes;
+    for (int c = 0; c < kMaxCols; ++c) s += vcols[c].bytes + ecols[c].bytes;
+    return s;
+  }
+  DevGraph view() const {
+    DevGraph g{};
+    g.n = n;
+    g.m = (int32_t)m;
+    g.out_off = out_off.as<int32_t>();
+    g.out_nbrs = out_nbrs.as<int32_t>();
+    g.in_off = in_off.as<int32_t>();
+    g.in_nbrs = in_nbrs.as<int32_t>();
+    g.src = src.as<int32_t>();
+    g.in_eid = in_eid.as<int32_t>();
+    g.n_vcols = n_vcols;
+    g.n_ecols = n_ecols;
+    for (int c = 0; c < kMaxCols; ++c) {
+      g.vcol[c] = vcols[c].as<int32_t>();
+      g.ecol[c] = ecols[c].as<int32_t>();
+    }
+    return g;
+  }
+};
+
+namespace {
+
+// ------------------------------------------------------------ graph ingest
+
+std::vector<int32_t> narrow_offsets(const int64_t* off, int32_t n, int64_t m, const char* name) {
+  if (off[0] != 0) fail(HPM_E_GRAPH, std::string(name) + "[0] must be 0");
+  std::vector<int32_t> out((size_t)n + 1);
+  for (int64_t i = 0; i <= n; ++i) {
+    if (i > 0 && off[i] < off[i - 1])
+      fail(HPM_E_GRAPH, std::string(name) + " decreases at " + std::to_string(i));
+    if (off[i] > m) fail(HPM_E_GRAPH, std::string(name) + " exceeds m at " + std::to_string(i));
+    out[i] = (int32_t)off[i];
+  }
+  if (off[n] != m) fail(HPM_E_GRAPH, std::string(name) + "[n] must equal m");
+  return out;
+}
+
+void upload(DevBuf& b, const void* host, size_t bytes, hipStream_t stream) {
+  b.ensure(bytes ? bytes : 4, stream);
+  if (bytes) hip_check(hipMemcpyAsync(b.p, host, bytes, hipMemcpyHostToDevice, stream), "upload");
+}
+
+std::string graph_error_text(uint32_t bits) {
+  std::string s;
+  if (bits & hpm::kErrRange) s += "neighbour id out of range; ";
+  if (bits & hpm::kErrSelfLoop) s += "self-loop; ";
+  if (bits & hpm::kErrUnsorted) s += "adjacency row not strictly ascending (unsorted or repeated arc); ";
+  if (bits & hpm::kErrTranspose) s += "in-CSR is not the transpose of the out-CSR; ";
+  return s;
+}
+
+// ------------------------------------------------------------ pattern plan
+
+struct PatternInfo {
+  int32_t k = 0;
+  std::vector<int32_t> src, dst;
+  std::vector<int32_t> indeg, outdeg;
+  std::vector<uint8_t> adj;  // [k*k], adj[a*k+b] = arc a->b
+};
+
+PatternInfo check_pattern(const hpm_pattern* p, int32_t n_vcols, int32_t n_ecols) {
+  if (!p) fail(HPM_E_ARG, "pattern is NULL");
+  if (p->k < 2 || p->k > kMaxK)
+    fail(HPM_E_PATTERN, "pattern must have 2.." + std::to_string(kMaxK) + " vertices");
+  const int32_t k = p->k;
+  if (p->n_arcs < 1 || p->n_arcs > k * (k - 1)) fail(HPM_E_PATTERN, "bad number of pattern arcs");
+  if (!p->src || !p->dst) fail(HPM_E_ARG, "pattern arc arrays are NULL");
+  if (n_vcols < 0 || n_vcols > kMaxCols || n_ecols < 0 || n_ecols > kMaxCols)
+    fail(HPM_E_ARG, "column counts out of range");
+  PatternInfo info;
+  info.k = k;
+  info.adj.assign((size_t)k * k, 0);
+  info.indeg.assign(k, 0);
+  info.outdeg.assign(k, 0);
+  for (int32_t i = 0; i < p->n_arcs; ++i) {
+    const int32_t a = p->src[i], b = p->dst[i];
+    if (a < 0 || a >= k || b < 0 || b >= k) fail(HPM_E_PATTERN, "pattern arc endpoint out of range");
+    if (a == b) fail(HPM_E_PATTERN, "pattern self-loop");
+    if (info.adj[(size_t)a * k + b]) fail(HPM_E_PATTERN, "repeated pattern arc");
+    info.adj[(size_t)a * k + b] = 1;
+    info.outdeg[a]++;
+    info.indeg[b]++;
+    info.src.push_back(a);
+    info.dst.push_back(b);
+  }
+  // weakly connected
+  std::vector<char> seen(k, 0);
+  std::vector<int32_t> stack{0};
+  seen[0] = 1;
+  int32_t nseen = 1;
+  while (!stack.empty()) {
+    const int32_t x = stack.back();
+    stack.pop_back();
+    for (int32_t y = 0; y < k; ++y)
+      if (!seen[y] && (info.adj[(size_t)x * k + y] || info.adj[(size_t)y * k + x])) {
+        seen[y] = 1;
+        ++nseen;
+        stack.push_back(y);
+      }
+  }
+  if (nseen != k) fail(HPM_E_PATTERN, "pattern is not weakly connected");
+  auto check_ops = [](const int32_t* op, const int32_t* val, int64_t count, const char* what) {
+    if (!op || count == 0) return;
+    if (!val) fail(HPM_E_ARG, std::string(what) + " values are NULL");
+    for (int64_t i = 0; i < count; ++i)
+      if (op[i] < HPM_ANY || op[i] > HPM_GE) fail(HPM_E_PATTERN, std::string("bad ") + what + " op");
+  };
+  check_ops(p->vop, p->vval, (int64_t)k * n_vcols, "vertex predicate");
+  check_ops(p->eop, p->eval, (int64_t)p->n_arcs * n_ecols, "arc predicate");
+  return info;
+}
+
+// Matching order (position -> original vertex), Sec. III-A, Alg. 1: rank
+// sigma(v) = (total degree, out-degree); start at the best-ranked vertex; then
+// take the best-ranked unplaced out-neighbour of the last placed vertex; if it
+// has none, the best-ranked unplaced vertex adjacent to any placed vertex
+// (keeps each position after the first connected to an earlier one, so the
+// first two positions always form a pattern arc).  Ties: smaller id.
+// With HPM_F_NO_REORDER: vertex 0 first, then the smallest-id unplaced vertex
+// adjacent to the placed ones.
+std::vector<int32_t> plan_order(const PatternInfo& P, uint32_t flags) {
+  const int32_t k = P.k;
+  auto better = [&](int32_t v, int32_t w) {  // is v ranked above w?
+    const int32_t tv = P.indeg[v] + P.outdeg[v], tw = P.indeg[w] + P.outdeg[w];
+    if (tv != tw) return tv > tw;
+    if (P.outdeg[v] != P.outdeg[w]) return P.outdeg[v] > P.outdeg[w];
+    return v < w;
+  };
+  auto adjacent = [&](int32_t a, int32_t b) {
+    return P.adj[(size_t)a * k + b] || P.adj[(size_t)b * k + a];
+  };
+  std::vector<int32_t> order;
+  std::vector<char> placed(k, 0);
+  const bool natural = (flags & HPM_F_NO_REORDER) != 0;
+  int32_t first = 0;
+  if (!natural)
+    for (int32_t v = 1; v < k; ++v)
+      if (better(v, first)) first = v;
+  order.push_back(first);
+  placed[first] = 1;
+  while ((int32_t)order.size() < k) {
+    int32_t pick = -1;
+    if (!natural) {
+      const int32_t u = order.back();
+      for (int32_t w = 0; w < k; ++w)
+        if (!placed[w] && P.adj[(size_t)u * k + w] && (pick < 0 || better(w, pick))) pick = w;
+    }
+    if (pick < 0) {
+      for (int32_t w = 0; w < k; ++w) {
+        if (placed[w]) continue;
+        bool touches = false;
+        for (int32_t x : order) touches = touches || adjacent(w, x);
+        if (!touches) continue;
+        if (pick < 0 || (natural ? w < pick : better(w, pick))) pick = w;
+      }
+    }
+    order.push_back(pick);
+    placed[pick] = 1;
+  }
+  return order;
+}
+
+void set_range(int32_t op, int32_t val, int32_t* lo, int32_t* hi) {
+  if (op == HPM_EQ) {
+    *lo = val;
+    *hi = val;
+  } else {  // HPM_GE
+    *lo = val;
+    *hi = INT32_MAX;
+  }
+}
+
+DevPlan build_dev_plan(const hpm_pattern* p, const PatternInfo& P, const std::vector<int32_t>& order,
+                       int32_t n_vcols, int32_t n_ecols, int mode) {
+  const int32_t k = P.k;
+  DevPlan d;
+  std::memset(&d, 0, sizeof(d));
+  d.k = k;
+  d.mode = mode;
+  std::vector<int32_t> pos(k);
+  for (int32_t i = 0; i < k; ++i) pos[order[i]] = i;
+  for (int32_t i = 0; i < k; ++i) {
+    const int32_t v = order[i];
+    d.orig[i] = v;
+    d.pin[i] = P.indeg[v];
+    d.pout[i] = P.outdeg[v];
+    for (int c = 0; c < kMaxCols; ++c) {
+      d.vlo[i][c] = INT32_MIN;
+      d.vhi[i][c] = INT32_MAX;
+    }
+    if (p->vop)
+      for (int32_t c = 0; c < n_vcols; ++c) {
+        const int32_t op = p->vop[(size_t)v * n_vcols + c];
+        if (op == HPM_ANY) continue;
+        d.vmask[i] |= 1u << c;
+        set_range(op, p->vval[(size_t)v * n_vcols + c], &d.vlo[i][c], &d.vhi[i][c]);
+      }
+  }
+  for (size_t i = 0; i < P.src.size(); ++i) {
+    const int32_t ps = pos[P.src[i]], pt = pos[P.dst[i]];
+    if (ps < pt)
+      d.fwd[pt] |= 1u << ps;
+    else
+      d.bwd[ps] |= 1u << pt;
+    for (int c = 0; c < kMaxCols; ++c) {
+      d.alo[ps][pt][c] = INT32_MIN;
+      d.ahi[ps][pt][c] = INT32_MAX;
+    }
+    if (p->eop)
+      for (int32_t c = 0; c < n_ecols; ++c) {
+        const int32_t op = p->eop[i * n_ecols + c];
+        if (op == HPM_ANY) continue;
+        d.amask[ps][pt] |= 1u << c;
+        set_range(op, p->eval[i * n_ecols + c], &d.alo[ps][pt][c], &d.ahi[ps][pt][c]);
+      }
+  }
+  const bool a01 = P.adj[(size_t)order[0] * k + order[1]] != 0;
+  const bool a10 = P.adj[(size_t)order[1] * k + order[0]] != 0;
+  if (!a01 && !a10) fail(HPM_E_INTERNAL, "first two positions are not adjacent");
+  d.mve_forward = a01 ? 1 : 0;
+  if (a01 && a10)
+    d.rev_rule = 1;
+  else
+    d.rev_rule = (mode == HPM_ISO) ? 2 : 0;
+  return d;
+}
+
+// ------------------------------------------------------------ matcher
+
+enum : int { kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3, kCntSlots = 4 };
+
+struct Matcher {
+  hpm_graph* G;
+  Workspace* W;
+  hipStream_t stream;
+  DevGraph g;
+  DevPlan host_plan;
+  int32_t k;
+  int32_t* maps;
+  uint64_t cap;
+  bool timing;
+  int max_grid;
+  int64_t cap2 = 0;     // depth-2 rows per arc chunk
+  int64_t chunk = 0;    // rows per frontier chunk at depth >= 3
+  hpm_match_stats st{};
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  size_t next_event = 0;
+
+  DevPlan* dplan() const { return W->plan.as<DevPlan>(); }
+  unsigned long long* counters() const { return W->counters.as<unsigned long long>(); }
+
+  hipEvent_t event() {
+    if (next_event == W->events.size()) {
+      hipEvent_t e;
+      hip_check(hipEventCreate(&e), "hipEventCreate");
+      W->events.push_back(e);
+    }
+    return W->events[next_event++];
+  }
+
+  template <class L>
+  void launch(int kind, L&& fn) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timing) {
+      a = event();
+      hip_check(hipEventRecord(a, stream), "hipEventRecord");
+    }
+    hip_check(fn(), "kernel launch");
+    if (timing) {
+      b = event();
+      hip_check(hipEventRecord(b, stream), "hipEventRecord");
+      pending.push_back({kind, a, b});
+    }
+    st.kernel_launches[kind]++;
+  }
+
+  // Synchronise the stream, fold pending event timings into the stats.
+  void sync() {
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    for (const Pending& p : pending) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime");
+      st.kernel_ms[p.kind] += ms;
+    }
+    pending.clear();
+    next_event = 0;
+  }
+
+  unsigned long long read_counter(int slot) {
+    hip_check(hipMemcpyAsync(W->host + slot, counters() + slot, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, stream),
+              "readback");
+    sync();
+    return W->host[slot];
+  }
+  int64_t read_i64(const int64_t* p) {
+    hip_check(hipMemcpyAsync(W->host + kCntSlots, p, sizeof(int64_t), hipMemcpyDeviceToHost, stream),
+              "readback");
+    sync();
+    return (int64_t)W->host[kCntSlots];
+  }
+  void zero_counter(int slot) {
+    hip_check(hipMemsetAsync(counters() + slot, 0, sizeof(unsigned long long), stream), "memset");
+  }
+
+  int grid_for(int64_t items, int64_t per_block) const {
+    int64_t b = (items + per_block - 1) / per_block;
+    b = std::max<int64_t>(8, std::min<int64_t>(b, max_grid));
+    return (int)((b + 7) / 8 * 8);  // tile mapping needs a multiple of the 8 XCDs
+  }
+
+  void ensure_depth(int32_t d, int64_t r_cap) {
+    const int64_t nb = (r_cap + hpm::kPivotTile - 1) / hpm::kPivotTile;
+    W->off[d].ensure((size_t)(r_cap + 1) * sizeof(int64_t), stream);
+    W->piv[d].ensure((size_t)std::max<int64_t>(r_cap, 1) * sizeof(int32_t), stream);
+    W->bsum[d].ensure((size_t)(nb + 1) * sizeof(int64_t), stream);
+  }
+
+  // Extend the r rows (each d entries) in `rows` to full embeddings.
+  void process_depth(int32_t d, const int32_t* rows, int64_t r) {
+    if (r == 0) return;
+    st.rows[d] += r;
+    int64_t* off = W->off[d].as<int64_t>();
+    int32_t* piv = W->piv[d].as<int32_t>();
+    int64_t* bsum = W->bsum[d].as<int64_t>();
+    launch(HPM_K_ROW_PIVOT, [&] {
+      return hpm::launch_row_pivot(g, dplan(), d, rows, (int32_t)r, piv, off, bsum, stream);
+    });
+    launch(HPM_K_PREFIX_SUM, [&] { return hpm::launch_scan_lengths(off, (int32_t)r, bsum, stream); });
+    const int64_t work = read_i64(off + r);
+    st.work[d] += (uint64_t)work;
+    if (work == 0) return;
+    if (d == k - 1) {
+      const int grid = grid_for(work, hpm::kExpandTile);
+      const int mode = maps ? 2 : 1;
+      launch(HPM_K_LAST_LEVEL, [&] {
+        return hpm::launch_expand(g, dplan(), d, rows, off, piv, (int32_t)r, 0, work, mode, maps,
+                                  counters() + kCntEmit, maps ? cap : 0,
+                                  W->partials.as<unsigned long long>(), grid, stream);
+      });
+      launch(HPM_K_REDUCE, [&] {
+        return hpm::launch_reduce_counts(W->partials.as<unsigned long long>(), grid,
+                                         counters() + kCntTotal,
+                                         reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
+                                         stream);
+      });
+      return;
+    }
+    for (int64_t w0 = 0; w0 < work; w0 += chunk) {
+      const int64_t w1 = std::min(work, w0 + chunk);
+      const int64_t n_items = w1 - w0;
+      st.chunks++;
+      W->rows[d + 1].ensure((size_t)n_items * (d + 1) * sizeof(int32_t), stream);
+      ensure_depth(d + 1, n_items);
+      int32_t* out = W->rows[d + 1].as<int32_t>();
+      zero_counter(kCntCursor);
+      const int grid = grid_for(n_items, hpm::kExpandTile);
+      launch(HPM_K_EXPAND, [&] {
+        return hpm::launch_expand(g, dplan(), d, rows, off, piv, (int32_t)r, w0, w1, 0, out,
+                                  counters() + kCntCursor, (unsigned long long)n_items,
+                                  W->partials.as<unsigned long long>(), grid, stream);
+      });
+      const int64_t r1 = (int64_t)read_counter(kCntCursor);
+      if (r1 > n_items) fail(HPM_E_INTERNAL, "frontier chunk overflow");
+      process_depth(d + 1, out, r1);
+    }
+  }
+
+  void run() {
+    const int64_t m = G->m;
+    st.arcs_scanned = (uint64_t)m;
+    launch(HPM_K_VERTEX_VALIDATOR, [&] {
+      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<uint8_t>(), stream);
+    });
+    if (k == 2) {
+      zero_counter(kCntCursor);
+      const int grid = grid_for(m, hpm::kScanTile);
+      launch(HPM_K_EDGE_SCAN, [&] {
+        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<uint8_t>(), 0, (int32_t)m,
+                                     maps ? 2 : 1, maps, counters() + kCntCursor,
+                                     maps ? cap : 0, grid, stream);
+      });
+      const uint64_t c = read_counter(kCntCursor);
+      st.survivors = c;
+      st.rows[2] = c;
+      st.count = c;
+      return;
+    }
+    for (int64_t e0 = 0; e0 < m; e0 += cap2) {
+      const int64_t e1 = std::min<int64_t>(m, e0 + cap2);
+      zero_counter(kCntCursor);
+      const int grid = grid_for(e1 - e0, hpm::kScanTile);
+      launch(HPM_K_EDGE_SCAN, [&] {
+        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<uint8_t>(), (int32_t)e0, (int32_t)e1,
+                                     0, W->rows2.as<int32_t>(), counters() + kCntCursor,
+                                     (unsigned long long)(e1 - e0), grid, stream);
+      });
+      const int64_t s2 = (int64_t)read_counter(kCntCursor);
+      if (s2 > e1 - e0) fail(HPM_E_INTERNAL, "scan overflow");
+      st.survivors += (uint64_t)s2;
+      process_depth(2, W->rows2.as<int32_t>(), s2);
+    }
+    st.count = read_counter(kCntTotal);
+    if (read_counter(kCntOverflow)) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
+  }
+};
+
+constexpr uint64_t kMinChunkRows = hpm::kExpandTile;
+
+}  // namespace
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int hpm_abi_version(void) { return HPM_ABI_VERSION; }
+
+const char* hpm_status_string(int status) {
+  switch (status) {
+    case HPM_OK: return "ok";
+    case HPM_E_ARG: return "invalid argument";
+    case HPM_E_GRAPH: return "malformed graph";
+    case HPM_E_PATTERN: return "malformed pattern";
+    case HPM_E_NOMEM: return "out of device memory or scratch budget too small";
+    case HPM_E_TRUNCATED: return "mapping buffer too small";
+    case HPM_E_OVERFLOW: return "count overflow";
+    case HPM_E_DEVICE: return "device error";
+    case HPM_E_UNSUPPORTED: return "unsupported size";
+    case HPM_E_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* hpm_last_error(void) { return t_error.c_str(); }
+
+int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_off,
+                     const int32_t* out_nbrs, const int64_t* in_off, const int32_t* in_nbrs,
+                     int32_t n_vcols, const int32_t* const* vcols, int32_t n_ecols,
+                     const int32_t* const* ecols, void* stream_) {
+  return guarded([&]() -> int {
+    if (!out) fail(HPM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || m < 0) fail(HPM_E_ARG, "negative size");
+    if (n >= INT32_MAX || m > INT32_MAX) fail(HPM_E_UNSUPPORTED, "n and m must be below 2^31 - 1");
+    if (!out_off || !in_off) fail(HPM_E_ARG, "offset arrays are NULL");
+    if (m > 0 && (!out_nbrs || !in_nbrs)) fail(HPM_E_ARG, "neighbour arrays are NULL");
+    if (n_vcols < 0 || n_vcols > kMaxCols || n_ecols < 0 || n_ecols > kMaxCols)
+      fail(HPM_E_ARG, "column counts must be 0..4");
+    if (n_vcols > 0 && !vcols) fail(HPM_E_ARG, "vcols is NULL");
+    if (n_ecols > 0 && !ecols) fail(HPM_E_ARG, "ecols is NULL");
+    for (int c = 0; c < n_vcols; ++c)
+      if (n > 0 && !vcols[c]) fail(HPM_E_ARG, "vertex column is NULL");
+    for (int c = 0; c < n_ecols; ++c)
+      if (m > 0 && !ecols[c]) fail(HPM_E_ARG, "arc column is NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    std::vector<int32_t> oo = narrow_offsets(out_off, n, m, "out_off");
+    std::vector<int32_t> io = narrow_offsets(in_off, n, m, "in_off");
+
+    std::unique_ptr<hpm_graph> G(new hpm_graph());
+    hip_check(hipGetDevice(&G->device), "hipGetDevice");
+    int cus = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, G->device),
+              "hipDeviceGetAttribute");
+    G->num_cus = cus > 0 ? cus : 256;
+    G->n = n;
+    G->m = m;
+    G->n_vcols = n_vcols;
+    G->n_ecols = n_ecols;
+    const size_t mb = (size_t)m * sizeof(int32_t);
+    upload(G->out_off, oo.data(), oo.size() * sizeof(int32_t), stream);
+    upload(G->in_off, io.data(), io.size() * sizeof(int32_t), stream);
+    upload(G->out_nbrs, out_nbrs, mb, stream);
+    upload(G->in_nbrs, in_nbrs, mb, stream);
+    for (int c = 0; c < n_vcols; ++c) upload(G->vcols[c], vcols[c], (size_t)n * 4, stream);
+    for (int c = 0; c < n_ecols; ++c) upload(G->ecols[c], ecols[c], mb, stream);
+    G->src.ensure(mb ? mb : 4, stream);
+    G->in_eid.ensure(mb ? mb : 4, stream);
+    DevBuf in_row, err;
+    in_row.ensure(mb ? mb : 4, stream);
+    err.ensure(sizeof(uint32_t), stream);
+    hip_check(hipMemsetAsync(err.p, 0, sizeof(uint32_t), stream), "memset");
+    uint32_t* e = err.as<uint32_t>();
+    const int32_t mi = (int32_t)m;
+    hip_check(hpm::launch_derive_rows(G->out_off.as<int32_t>(), n, mi, G->src.as<int32_t>(), stream),
+              "derive rows");
+    hip_check(hpm::launch_derive_rows(G->in_off.as<int32_t>(), n, mi, in_row.as<int32_t>(), stream),
+              "derive rows");
+    hip_check(hpm::launch_check_rows(G->out_off.as<int32_t>(), G->out_nbrs.as<int32_t>(),
+                                     G->src.as<int32_t>(), n, mi, e, stream),
+              "check rows");
+    hip_check(hpm::launch_check_rows(G->in_off.as<int32_t>(), G->in_nbrs.as<int32_t>(),
+                                     in_row.as<int32_t>(), n, mi, e, stream),
+              "check rows");
+    hip_check(hpm::launch_transpose_ids(G->in_off.as<int32_t>(), G->in_nbrs.as<int32_t>(),
+                                        in_row.as<int32_t>(), G->out_off.as<int32_t>(),
+                                        G->out_nbrs.as<int32_t>(), n, mi, G->in_eid.as<int32_t>(),
+                                        e, stream),
+              "transpose ids");
+    uint32_t bits = 0;
+    hip_check(hipMemcpyAsync(&bits, e, sizeof(bits), hipMemcpyDeviceToHost, stream), "readback");
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (bits) fail(HPM_E_GRAPH, graph_error_text(bits));
+    *out = G.release();
+    return HPM_OK;
+  });
+}
+
+int hpm_graph_destroy(hpm_graph* g) {
+  return guarded([&]() -> int {
+    if (!g) return HPM_OK;
+    int cur = 0;
+    const int dev = g->device;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    delete g;
+    if (cur != dev) (void)hipSetDevice(cur);
+    return HPM_OK;
+  });
+}
+
+int hpm_graph_info(const hpm_graph* g, int32_t* n, int64_t* m, uint64_t* device_bytes) {
+  return guarded([&]() -> int {
+    if (!g) fail(HPM_E_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (device_bytes) *device_bytes = g->bytes();
+    return HPM_OK;
+  });
+}
+
+int hpm_plan_order(const hpm_pattern* p, int32_t n_vcols, int32_t n_ecols, uint32_t flags,
+                   int32_t* order) {
+  return guarded([&]() -> int {
+    if (!order) fail(HPM_E_ARG, "order is NULL");
+    PatternInfo info = check_pattern(p, n_vcols, n_ecols);
+    std::vector<int32_t> o = plan_order(info, flags);
+    std::copy(o.begin(), o.end(), order);
+    return HPM_OK;
+  });
+}
+
+int hpm_last_stats(hpm_match_stats* out) {
+  return guarded([&]() -> int {
+    if (!out) fail(HPM_E_ARG, "out is NULL");
+    *out = t_stats;
+    return HPM_OK;
+  });
+}
+
+int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream_,
+              const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap) {
+  return guarded([&]() -> int {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (!count) fail(HPM_E_ARG, "count is NULL");
+    if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
+    uint32_t flags = 0;
+    uint64_t budget = 0;
+    if (opts) {
+      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
+      flags = opts->flags;
+      budget = opts->hbm_budget_bytes;
+    }
+    hpm_graph* G = const_cast<hpm_graph*>(gc);
+    PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
+    const int32_t k = info.k;
+    if (mappings && cap > (uint64_t)INT64_MAX / (uint64_t)k) fail(HPM_E_ARG, "cap too large");
+    std::vector<int32_t> order = plan_order(info, flags);
+    DevPlan plan = build_dev_plan(p, info, order, G->n_vcols, G->n_ecols, (int)mode);
+
+    int cur = 0;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    struct DeviceGuard {
+      int prev, want;
+      DeviceGuard(int p_, int w_) : prev(p_), want(w_) {
+        if (prev != want) hip_check(hipSetDevice(want), "hipSetDevice");
+      }
+      ~DeviceGuard() {
+        if (prev != want) (void)hipSetDevice(prev);
+      }
+    } dg(cur, G->device);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+
+    if (budget == 0) {
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      budget = free_b / 4;
+    }
+
+    // Scratch layout and its budget.  Fixed part: plan, vertex flags, counters,
+    // per-block partial counts.  Depth 2 costs 21 B per row of an arc chunk
+    // (row 8, prefix 8, pivot 4, block sums); depth d >= 3 costs 4d + 13 B per row.
+    const int max_grid = std::max(64, G->num_cus * 8);
+    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n + 64 +
+                           (uint64_t)max_grid * sizeof(unsigned long long) + 4096;
+    if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
+    uint64_t avail = budget - fixed;
+    int64_t cap2 = 0, chunk = 0;
+    if (k >= 3) {
+      uint64_t per_row_deep = 0;
+      for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += 4 * (uint64_t)d + 13;
+      const uint64_t m_round =
+          ((uint64_t)G->m + hpm::kScanTile - 1) / hpm::kScanTile * hpm::kScanTile;
+      uint64_t c2 = std::min<uint64_t>(std::max<uint64_t>(m_round, hpm::kScanTile),
+                                       (per_row_deep ? avail / 2 : avail) / 21);
+      c2 = c2 / hpm::kScanTile * hpm::kScanTile;
+      c2 = std::min<uint64_t>(c2, (uint64_t)INT32_MAX / hpm::kScanTile * hpm::kScanTile);
+      if (c2 < (uint64_t)hpm::kScanTile) fail(HPM_E_NOMEM, "scratch budget below one arc chunk");
+      cap2 = (int64_t)c2;
+      if (per_row_deep) {
+        uint64_t c = (avail - c2 * 21) / per_row_deep;
+        c = std::min<uint64_t>(c, (uint64_t)1 << 30);
+        if (c < kMinChunkRows) fail(HPM_E_NOMEM, "scratch budget below one frontier chunk");
+        chunk = (int64_t)c;
+      }
+    }
+
+    Workspace* W = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(G->mu);
+      if (!G->pool.empty()) {
+        W = G->pool.back();
+        G->pool.pop_back();
+      }
+    }
+    if (!W) W = new Workspace();
+    struct Return {
+      hpm_graph* G;
+      Workspace* W;
+      ~Return() {
+        std::lock_guard<std::mutex> lk(G->mu);
+        G->pool.push_back(W);
+      }
+    } ret{G, W};
+    if (W->held() > budget) {
+      hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+      W->release_all();
+    }
+    if (!W->host)
+      hip_check(hipHostMalloc((void**)&W->host, 8 * sizeof(unsigned long long)), "hipHostMalloc");
+    if (!W->host_plan)
+      hip_check(hipHostMalloc((void**)&W->host_plan, sizeof(DevPlan)), "hipHostMalloc");
+
+    Matcher M{G, W, stream, G->view(), plan, k, mappings, mappings ? cap : 0,
+              (flags & HPM_F_TIMING) != 0, max_grid};
+    M.cap2 = cap2;
+    M.chunk = chunk;
+    W->plan.ensure(sizeof(DevPlan), stream);
+    W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1), stream);
+    W->counters.ensure(8 * sizeof(unsigned long long), stream);
+    W->partials.ensure((size_t)max_grid * sizeof(unsigned long long), stream);
+    if (k >= 3) {
+      const int64_t rows2 = std::min<int64_t>(cap2, std::max<int64_t>(G->m, 1));
+      W->rows2.ensure((size_t)rows2 * 2 * sizeof(int32_t), stream);
+      M.ensure_depth(2, rows2);
+    }
+    // The plan goes through pinned memory so the copy is truly asynchronous.
+    *W->host_plan = plan;
+    hip_check(hipMemcpyAsync(W->plan.p, W->host_plan, sizeof(DevPlan), hipMemcpyHostToDevice,
+                             stream),
+              "plan upload");
+    hip_check(hipMemsetAsync(W->counters.p, 0, 8 * sizeof(unsigned long long), stream), "memset");
+    M.run();
+    uint64_t emitted = 0;
+    if (mappings && k >= 3) emitted = M.read_counter(kCntEmit);
+    M.sync();
+    M.st.struct_size = sizeof(hpm_match_stats);
+    M.st.scratch_bytes = W->held();
+    M.st.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *count = M.st.count;
+    t_stats = M.st;
+    (void)emitted;
+    if (mappings && M.st.count > cap) {
+      t_error = "count " + std::to_string(M.st.count) + " exceeds cap " + std::to_string(cap);
+      return HPM_E_TRUNCATED;
+    }
+    return HPM_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""Python binding of libhpm (ctypes).  Argument marshalling only.
+
+Every step of matching runs in the HIP library; this module converts numpy
+arrays and torch device buffers/streams into the pointers the C ABI
+(include/hpm.h) takes.  torch supplies device memory for mapping output and
+the current stream; nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhpm.so")
+
+OK, E_ARG, E_GRAPH, E_PATTERN, E_NOMEM, E_TRUNCATED, E_OVERFLOW, E_DEVICE, E_UNSUPPORTED, \
+    E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+ISO, MONO = 0, 1
+ANY, EQ, GE = 0, 1, 2
+F_NO_REORDER = 0x1
+F_TIMING = 0x2
+MAX_K = 16
+KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand", "last_level",
+           "reduce")
+
+# Every function include/hpm.h declares.
+EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
+           "hpm_plan_order", "hpm_last_stats", "hpm_status_string", "hpm_last_error",
+           "hpm_abi_version")
+
+
+class HpmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class _Pattern(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n_arcs", ctypes.c_int32),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("vop", ctypes.c_void_p), ("vval", ctypes.c_void_p),
+                ("eop", ctypes.c_void_p), ("eval", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("arcs_scanned", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
+                ("rows", ctypes.c_uint64 * (MAX_K + 1)), ("work", ctypes.c_uint64 * (MAX_K + 1)),
+                ("chunks", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
+                ("kernel_launches", ctypes.c_uint64 * len(KERNELS)),
+                ("kernel_ms", ctypes.c_double * len(KERNELS)), ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhpm.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2507_04130_amd.build`")
+    # torch ships its own HIP runtime with the same soname as ROCm's; loading it
+    # first makes libhpm bind to that one copy, so streams and device pointers
+    # from torch are valid inside the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    lib.hpm_graph_create.argtypes = [ctypes.POINTER(P), I32, I64, P, P, P, P, I32, P, I32, P, P]
+    lib.hpm_graph_destroy.argtypes = [P]
+    lib.hpm_graph_info.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64),
+                                   ctypes.POINTER(U64)]
+    lib.hpm_match.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
+                              ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
+    lib.hpm_plan_order.argtypes = [ctypes.POINTER(_Pattern), I32, I32, ctypes.c_uint32, P]
+    lib.hpm_last_stats.argtypes = [ctypes.POINTER(_Stats)]
+    lib.hpm_status_string.argtypes = [ctypes.c_int]
+    lib.hpm_status_string.restype = ctypes.c_char_p
+    lib.hpm_last_error.restype = ctypes.c_char_p
+    lib.hpm_abi_version.restype = ctypes.c_int
+    for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
+                 "hpm_plan_order", "hpm_last_stats"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        lib = load()
+        msg = lib.hpm_last_error().decode() or lib.hpm_status_string(status).decode()
+        raise HpmError(status, msg)
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Graph:
+    """A target graph resident in device memory (hpm_graph_create)."""
+
+    def __init__(self, out_off, out_nbrs, in_off, in_nbrs, vcols=(), ecols=(), stream=None):
+        lib = load()
+        self._keep = [np.ascontiguousarray(out_off, dtype=np.int64),
+                      _i32(out_nbrs), np.ascontiguousarray(in_off, dtype=np.int64),
+                      _i32(in_nbrs)]
+        n = self._keep[0].shape[0] - 1
+        m = self._keep[1].shape[0]
+        vc = [_i32(c) for c in vcols]
+        ec = [_i32(c) for c in ecols]
+        vptrs = (ctypes.c_void_p * max(1, len(vc)))(*[c.ctypes.data for c in vc])
+        eptrs = (ctypes.c_void_p * max(1, len(ec)))(*[c.ctypes.data for c in ec])
+        h = ctypes.c_void_p()
+        _check(lib.hpm_graph_create(ctypes.byref(h), n, m, _ptr(self._keep[0]),
+                                    _ptr(self._keep[1]), _ptr(self._keep[2]),
+                                    _ptr(self._keep[3]), len(vc), vptrs if vc else None,
+                                    len(ec), eptrs if ec else None, _stream_handle(stream)))
+        self._h = h
+        self._keep = None
+        self.n_vcols = len(vc)
+        self.n_ecols = len(ec)
+
+    @classmethod
+    def from_host(cls, hg, stream=None) -> "Graph":
+        """From any object with out_off/out_nbrs/in_off/in_nbrs/vcols/ecols arrays."""
+        return cls(hg.out_off, hg.out_nbrs, hg.in_off, hg.in_nbrs, hg.vcols, hg.ecols, stream)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def info(self):
+        n, m, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_uint64()
+        _check(load().hpm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
+                                     ctypes.byref(b)))
+        return {"n": n.value, "m": m.value, "device_bytes": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hpm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _pattern_struct(p):
+    arrs = {name: _i32(getattr(p, name)) for name in ("src", "dst", "vop", "vval", "eop", "eval")}
+    s = _Pattern(int(p.k), int(arrs["src"].shape[0]), *[_ptr(arrs[n]) for n in
+                 ("src", "dst", "vop", "vval", "eop", "eval")])
+    return s, arrs
+
+
+def plan_order(p, n_vcols: int = 1, n_ecols: int = 1, flags: int = 0) -> list:
+    """Matching order (position -> pattern vertex) the library uses; host only."""
+    s, keep = _pattern_struct(p)
+    out = np.zeros(int(p.k), dtype=np.int32)
+    _check(load().hpm_plan_order(ctypes.byref(s), n_vcols, n_ecols, flags, _ptr(out)))
+    return out.tolist()
+
+
+def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None, stream=None,
+          budget: int | None = None, flags: int = 0):
+    """Count embeddings of pattern p in g; optionally return them.
+
+    Returns (count, rows) where rows is None or an int32 torch tensor [count, k]
+    on the current device (original pattern-vertex order, unspecified row
+    order).  With mappings=True and cap=None the count is taken first and the
+    buffer sized to it (two calls).
+    """
+    lib = load()
+    nv = 0 if p.vop is None else np.asarray(p.vop).shape[-1]
+    ne = 0 if p.eop is None else np.asarray(p.eop).shape[-1]
+    if (p.vop is not None and nv != g.n_vcols) or (p.eop is not None and ne != g.n_ecols):
+        raise HpmError(E_PATTERN, f"pattern has {nv} vertex / {ne} arc predicate columns, "
+                                  f"graph has {g.n_vcols} / {g.n_ecols}")
+    s, keep = _pattern_struct(p)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0))
+    cnt = ctypes.c_uint64()
+    sh = _stream_handle(stream)
+    if not mappings:
+        _check(lib.hpm_match(g.handle, ctypes.byref(s), int(mode), sh, ctypes.byref(opts),
+                             ctypes.byref(cnt), None, 0))
+        return int(cnt.value), None
+    import torch
+    if cap is None:
+        _check(lib.hpm_match(g.handle, ctypes.byref(s), int(mode), sh, ctypes.byref(opts),
+                             ctypes.byref(cnt), None, 0))
+        cap = int(cnt.value)
+    buf = torch.empty((max(int(cap), 1), int(p.k)), dtype=torch.int32, device="cuda")
+    st = lib.hpm_match(g.handle, ctypes.byref(s), int(mode), sh, ctypes.byref(opts),
+                       ctypes.byref(cnt), ctypes.c_void_p(buf.data_ptr()), int(cap))
+    _check(st)
+    return int(cnt.value), buf[: int(cnt.value)]
+
+
+def last_stats() -> dict:
+    """Statistics of this thread's most recent successful match."""
+    s = _Stats()
+    _check(load().hpm_last_stats(ctypes.byref(s)))
+    return {
+        "count": s.count, "arcs_scanned": s.arcs_scanned, "survivors": s.survivors,
+        "rows": list(s.rows), "work": list(s.work), "chunks": s.chunks,
+        "scratch_bytes": s.scratch_bytes,
+        "kernel_launches": dict(zip(KERNELS, list(s.kernel_launches))),
+        "kernel_ms": dict(zip(KERNELS, list(s.kernel_ms))), "ms_total": s.ms_total,
+    }
+
+
+def status_string(status: int) -> str:
+    return load().hpm_status_string(status).decode()
+
+
+def abi_version() -> int:
+    return load().hpm_abi_version()

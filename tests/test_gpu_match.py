@@ -1,0 +1,287 @@
+"""Parity of the HIP matcher with the CPU oracle (GPU; calls through the C ABI).
+
+Counts and sorted mapping sets must be bit-exact.  Inputs are seeded: random
+small graphs, the hand-worked example, the ER workload and its companions,
+scaled-down R-MAT graphs with the benchmark motifs (several tiles plus a
+ragged tail), and invariances (matching order, chunked frontiers, relabelling).
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_04130_amd as hpm
+from paper_2507_04130_amd import hpm as hb
+from synth import configs
+from synth.graphs import erdos_renyi, from_dense, permute_vertices, rmat
+from synth.patterns import EQ, GE, ISO, MONO, MOTIFS, make_pattern, motif, random_pattern
+from tests import pins
+from tests.cases import (load_hand_example, random_small_graph, random_small_pattern)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def lexsorted(rows):
+    rows = np.asarray(rows)
+    if rows.shape[0] == 0:
+        return rows.reshape(0, rows.shape[1] if rows.ndim == 2 else 0)
+    return rows[np.lexsort(rows.T[::-1])]
+
+
+def gpu_rows(dg, p, mode, **kw):
+    cnt, t = hpm.match(dg, p, mode, mappings=True, **kw)
+    rows = t.cpu().numpy() if t is not None else np.zeros((0, p.k), np.int32)
+    assert rows.shape == (cnt, p.k)
+    return cnt, lexsorted(rows)
+
+
+def assert_parity(g, dg, p, mode, label="", **kw):
+    want = oracle.match(g, p, mode, threads=8)
+    cnt, rows = gpu_rows(dg, p, mode, **kw)
+    assert cnt == want.count, f"{label}: count {cnt} != oracle {want.count}"
+    np.testing.assert_array_equal(rows, want.rows, err_msg=label)
+    c2, _ = hpm.match(dg, p, mode, **kw)
+    assert c2 == want.count
+    return want.count
+
+
+def test_hand_example():
+    g, cases = load_hand_example()
+    say("hand example")
+    dg = hpm.Graph.from_host(g)
+    for name, p, mode, rows in cases:
+        cnt, got = gpu_rows(dg, p, mode)
+        assert cnt == rows.shape[0], name
+        np.testing.assert_array_equal(got, rows, err_msg=name)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_small_graphs(seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(2, 40))
+    nv = int(rng.integers(0, 3))
+    ne = int(rng.integers(0, 3))
+    g = random_small_graph(rng, n, float(rng.uniform(0.05, 0.6)), max(nv, 1), max(ne, 1))
+    g.vcols = g.vcols[:nv]
+    g.ecols = g.ecols[:ne]
+    k = int(rng.integers(2, min(n, 6) + 1)) if n >= 2 else 2
+    p = random_small_pattern(rng, k, max(nv, 1), max(ne, 1))
+    p.vop, p.vval = p.vop[:, :nv].copy(), p.vval[:, :nv].copy()
+    p.eop, p.eval = p.eop[:, :ne].copy(), p.eval[:, :ne].copy()
+    say(f"random seed={seed} n={n} m={g.m} k={k} arcs={p.n_arcs} nv={nv} ne={ne}")
+    dg = hpm.Graph.from_host(g)
+    for mode in (ISO, MONO):
+        assert_parity(g, dg, p, mode, f"seed {seed} mode {mode}")
+
+
+def test_c1_and_companions():
+    g = configs.c1_graph()
+    dg = hpm.Graph.from_host(g)
+    p = configs.c1_pattern()
+    say("c1")
+    c = assert_parity(g, dg, p, ISO, "c1")
+    assert c == pins.trace_cycle3(g, (0, 1, 2), 0, ISO)
+    pu = configs.c1u_pattern()
+    for mode in (ISO, MONO):
+        c = assert_parity(g, dg, pu, mode, "c1u")
+        gu = erdos_renyi(1000, 5000, configs.GRAPH_SEEDS["c1"])
+        gu.vcols = [np.zeros(g.n, np.int32)]
+        gu.ecols = [np.zeros(g.m, np.int32)]
+        assert c == pins.trace_cycle3(gu, (0, 0, 0), 0, mode)
+    gd = configs.c1d_graph()
+    dgd = hpm.Graph.from_host(gd)
+    for mode in (ISO, MONO):
+        c = assert_parity(gd, dgd, p, mode, "c1d")
+        assert c == pins.trace_cycle3(gd, (0, 1, 2), 0, mode)
+
+
+@pytest.mark.parametrize("scale", [10, 13])
+def test_rmat_motifs(scale):
+    g = configs.c2_graph(scale=scale)
+    dg = hpm.Graph.from_host(g)
+    for p, mode in configs.c2_runs():
+        say(f"rmat scale={scale} {p.name} mode={mode}")
+        assert_parity(g, dg, p, mode, f"{p.name}/{mode}")
+
+
+def test_unlabelled_rmat_4_vertex_motifs():
+    g = rmat(11, 1 << 14, seed=31)
+    dg = hpm.Graph.from_host(g)
+    for name in ("cycle4", "ffl_tail", "star3_back", "clique4_minus1", "cycle3"):
+        p = motif(name)
+        for mode in (ISO, MONO):
+            say(f"unlabelled {name} {mode}")
+            assert_parity(g, dg, p, mode, name)
+
+
+def test_five_vertex_motifs_connectome_shape():
+    from synth.graphs import connectome
+    g = connectome(30_000, 240_000, seed=8)
+    dg = hpm.Graph.from_host(g)
+    for name in configs.C3_MOTIFS:
+        p = motif(name, elabels=[3] * len(MOTIFS[name][1]), eop=GE)
+        for mode in (ISO, MONO):
+            say(f"connectome {name} {mode}")
+            assert_parity(g, dg, p, mode, name)
+
+
+def test_two_vertex_patterns():
+    g = erdos_renyi(300, 4000, seed=17)
+    dg = hpm.Graph.from_host(g)
+    pats = [
+        make_pattern(2, [(0, 1)], 1, 1, [[(EQ, 1)], [(EQ, 2)]], [[(EQ, 0)]]),
+        make_pattern(2, [(1, 0)], 1, 1, [[(EQ, 1)], [(GE, 2)]], None),
+        make_pattern(2, [(0, 1), (1, 0)], 1, 1, None, [[(EQ, 1)], [(GE, 1)]]),
+        make_pattern(2, [(0, 1)], 1, 1),
+    ]
+    for p in pats:
+        for mode in (ISO, MONO):
+            assert_parity(g, dg, p, mode, f"k2 {p.arcs()}")
+
+
+def test_random_patterns_up_to_eight_vertices():
+    g = configs.c2_graph(scale=11)
+    dg = hpm.Graph.from_host(g)
+    rng = np.random.default_rng(42)
+    for i in range(24):
+        p = random_pattern(rng, kmin=3, kmax=8)
+        mode = ISO if i % 2 else MONO
+        say(f"random pattern {i} k={p.k} arcs={p.n_arcs} mode={mode}")
+        assert_parity(g, dg, p, mode, f"rp{i}")
+
+
+def test_largest_pattern_sixteen_vertices():
+    # 16-vertex directed path on a dense small graph (all labels equal)
+    A = (np.random.default_rng(3).random((20, 20)) < 0.35).astype(np.int64)
+    np.fill_diagonal(A, 0)
+    g = from_dense(A, [np.zeros(20)], [np.zeros((20, 20))])
+    dg = hpm.Graph.from_host(g)
+    p = make_pattern(16, [(i, i + 1) for i in range(15)], 1, 1)
+    want = oracle.match(g, p, MONO, threads=8, rows=False)
+    got, _ = hpm.match(dg, p, MONO)
+    assert got == want.count
+    pi = make_pattern(6, [(i, i + 1) for i in range(5)], 1, 1)
+    assert_parity(g, dg, pi, ISO, "path6 iso")
+
+
+def test_reorder_and_budget_invariance():
+    g = configs.c2_graph(scale=12)
+    dg = hpm.Graph.from_host(g)
+    for p, mode in configs.c2_runs():
+        base_cnt, base = gpu_rows(dg, p, mode)
+        c1, r1 = gpu_rows(dg, p, mode, flags=hpm.F_NO_REORDER)
+        assert c1 == base_cnt
+        np.testing.assert_array_equal(r1, base)
+        # a small scratch budget forces several arc chunks and frontier chunks
+        c2, r2 = gpu_rows(dg, p, mode, budget=600_000)
+        st = hpm.last_stats()
+        assert c2 == base_cnt
+        np.testing.assert_array_equal(r2, base)
+        say(f"budget {p.name}/{mode}: chunks={st['chunks']} count={c2}")
+
+
+def test_relabelled_target():
+    g = configs.c2_graph(scale=11)
+    perm = np.random.default_rng(9).permutation(g.n)
+    gp = permute_vertices(g, perm)
+    dg, dgp = hpm.Graph.from_host(g), hpm.Graph.from_host(gp)
+    for p, mode in configs.c2_runs()[:4]:
+        c, r = gpu_rows(dg, p, mode)
+        cp, rp = gpu_rows(dgp, p, mode)
+        assert c == cp
+        np.testing.assert_array_equal(lexsorted(perm[r]), rp)
+
+
+def test_empty_and_tiny_graphs():
+    p = motif("cycle3")
+    for n in (0, 1, 2, 3):
+        A = np.zeros((n, n), dtype=np.int64)
+        if n == 3:
+            A[0, 1] = A[1, 2] = A[2, 0] = 1
+        g = from_dense(A, [np.zeros(n)], [np.zeros((n, n))])
+        dg = hpm.Graph.from_host(g)
+        for mode in (ISO, MONO):
+            cnt, rows = gpu_rows(dg, p, mode)
+            assert cnt == (3 if n == 3 else 0)
+
+
+def test_truncated_and_nomem():
+    g = configs.c1d_graph()
+    dg = hpm.Graph.from_host(g)
+    p = configs.c1u_pattern()
+    total, _ = hpm.match(dg, p, MONO)
+    assert total > 10
+    with pytest.raises(hpm.HpmError) as ei:
+        hpm.match(dg, p, MONO, mappings=True, cap=10)
+    assert ei.value.status == hb.E_TRUNCATED
+    with pytest.raises(hpm.HpmError) as ei:
+        hpm.match(dg, p, MONO, budget=1000)
+    assert ei.value.status == hb.E_NOMEM
+    # the graph is still usable after errors
+    assert hpm.match(dg, p, MONO)[0] == total
+
+
+def _create_status(n, arcs, in_arcs=None):
+    lib = hpm.load()
+    arcs = np.array(arcs, dtype=np.int64).reshape(-1, 2)
+    in_arcs = arcs if in_arcs is None else np.array(in_arcs, dtype=np.int64).reshape(-1, 2)
+    m = arcs.shape[0]
+    out_off = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(arcs[:, 0], minlength=n), out=out_off[1:])
+    in_off = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(in_arcs[:, 1], minlength=n), out=in_off[1:])
+    out_nbrs = arcs[:, 1].astype(np.int32)         # rows keep the given order
+    order = np.lexsort((in_arcs[:, 0], in_arcs[:, 1]))
+    in_nbrs = in_arcs[order, 0].astype(np.int32)
+    h = ctypes.c_void_p()
+    st = lib.hpm_graph_create(ctypes.byref(h), n, m, out_off.ctypes.data, out_nbrs.ctypes.data,
+                              in_off.ctypes.data, in_nbrs.ctypes.data, 0, None, 0, None, None)
+    if st == 0:
+        lib.hpm_graph_destroy(h)
+    return st
+
+
+def test_graph_create_errors():
+    assert _create_status(3, [(0, 1), (1, 2), (2, 0)]) == hb.OK
+    assert _create_status(3, [(0, 2), (0, 1), (1, 2)]) == hb.E_GRAPH            # unsorted row
+    assert _create_status(3, [(0, 1), (0, 1), (1, 2)]) == hb.E_GRAPH            # repeat
+    assert _create_status(3, [(0, 1), (1, 1), (1, 2)]) == hb.E_GRAPH            # self-loop
+    assert _create_status(3, [(0, 1), (1, 2), (2, 0)],
+                          [(0, 1), (1, 2), (2, 1)]) == hb.E_GRAPH               # not transpose
+    lib = hpm.load()
+    h = ctypes.c_void_p()
+    off = np.array([0, 1, 2], np.int64)
+    bad = np.array([1, 7], np.int32)                                            # id out of range
+    assert lib.hpm_graph_create(ctypes.byref(h), 2, 2, off.ctypes.data, bad.ctypes.data,
+                                off.ctypes.data, bad.ctypes.data, 0, None, 0, None,
+                                None) == hb.E_GRAPH
+
+
+def test_pattern_errors_and_column_mismatch():
+    g = configs.c1_graph()
+    dg = hpm.Graph.from_host(g)
+    p = make_pattern(4, [(0, 1), (2, 3)], 1, 1)
+    with pytest.raises(hpm.HpmError) as ei:
+        hpm.match(dg, p, ISO)
+    assert ei.value.status == hb.E_PATTERN
+    p2 = make_pattern(3, [(0, 1), (1, 2)], 2, 1)   # two vertex columns, graph has one
+    with pytest.raises(hpm.HpmError):
+        hpm.match(dg, p2, ISO)
+
+
+def test_repeated_calls_are_deterministic():
+    g = configs.c2_graph(scale=12)
+    dg = hpm.Graph.from_host(g)
+    p, mode = configs.c2_runs()[4]
+    first = gpu_rows(dg, p, mode)
+    for _ in range(3):
+        again = gpu_rows(dg, p, mode)
+        assert again[0] == first[0]
+        np.testing.assert_array_equal(again[1], first[1])

@@ -1,0 +1,155 @@
+"""libhpm on the CPU: symbols, the host-side planner and host-side argument checks.
+
+No kernel runs here.  hpm_plan_order is host-only; hpm_graph_create rejects
+malformed offsets before it touches the device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2507_04130_amd as hpm
+from paper_2507_04130_amd import hpm as hb
+from synth.patterns import MOTIFS, is_weakly_connected, make_pattern, motif, random_pattern
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "hpm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(hpm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = hpm.load()
+    declared = _header_functions()
+    assert set(declared) == set(hb.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert hpm.abi_version() == 1
+
+
+def test_status_strings():
+    for code in range(0, -10, -1):
+        assert hpm.status_string(code) not in ("", "unknown status")
+    assert hpm.status_string(-42) == "unknown status"
+
+
+def _check_order(p, order):
+    k = p.k
+    arcs = set(p.arcs())
+    assert sorted(order) == list(range(k))            # Prop. 1: a permutation
+    adj = lambda a, b: (a, b) in arcs or (b, a) in arcs
+    assert adj(order[0], order[1])                    # positions 0,1 form a pattern arc
+    for i in range(1, k):                             # every later position touches an earlier one
+        assert any(adj(order[i], order[j]) for j in range(i))
+
+
+def _sigma(p):
+    indeg = np.bincount(p.dst, minlength=p.k)
+    outdeg = np.bincount(p.src, minlength=p.k)
+    return indeg + outdeg, outdeg
+
+
+def test_plan_order_follows_structural_reordering():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        p = random_pattern(rng, kmin=2, kmax=12)
+        order = hpm.plan_order(p, 1, 1)
+        _check_order(p, order)
+        tot, out = _sigma(p)
+        # first position: best (total degree, out-degree), ties to the smaller id
+        best = max(range(p.k), key=lambda v: (tot[v], out[v], -v))
+        assert order[0] == best
+        # whenever the last placed vertex has unplaced out-neighbours, the next
+        # position is the best-ranked of them
+        arcs = set(p.arcs())
+        for i in range(1, p.k):
+            u = order[i - 1]
+            nbrs = [w for w in range(p.k) if (u, w) in arcs and w not in order[:i]]
+            if nbrs:
+                assert order[i] == max(nbrs, key=lambda v: (tot[v], out[v], -v))
+
+
+def test_plan_order_repairs_non_adjacent_start():
+    # l1..l4 -> s, l1 -> m, m -> p, m -> q: s ranks first but is a sink; the plain
+    # rule would continue with m, which is not adjacent to s.
+    s, l1, l2, l3, l4, m, pp, q = range(8)
+    arcs = [(l1, s), (l2, s), (l3, s), (l4, s), (l1, m), (m, pp), (m, q)]
+    p = make_pattern(8, arcs, 1, 1)
+    order = hpm.plan_order(p, 1, 1)
+    assert order[0] == s
+    assert order[1] == l1
+    _check_order(p, order)
+
+
+def test_plan_order_no_reorder_keeps_ids():
+    rng = np.random.default_rng(1)
+    for _ in range(100):
+        p = random_pattern(rng, kmin=2, kmax=10)
+        order = hpm.plan_order(p, 1, 1, hpm.F_NO_REORDER)
+        _check_order(p, order)
+        assert order[0] == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(k=1, arcs=[]),
+    dict(k=17, arcs=[(i, i + 1) for i in range(16)]),
+    dict(k=3, arcs=[(0, 0), (0, 1), (1, 2)]),
+    dict(k=3, arcs=[(0, 1), (0, 1), (1, 2)]),
+    dict(k=4, arcs=[(0, 1), (2, 3)]),
+    dict(k=3, arcs=[(0, 1), (1, 5)]),
+])
+def test_plan_order_rejects_bad_patterns(bad):
+    k = bad["k"]
+    arcs = bad["arcs"] or [(0, 0)]
+    p = make_pattern(max(k, 1), arcs, 1, 1)
+    p.k = k
+    with pytest.raises(hpm.HpmError) as ei:
+        hpm.plan_order(p, 1, 1)
+    assert ei.value.status == hb.E_PATTERN
+
+
+def test_plan_order_rejects_bad_ops():
+    p = motif("cycle3", vlabels=[0, 1, 2])
+    p.vop[1, 0] = 7
+    with pytest.raises(hpm.HpmError) as ei:
+        hpm.plan_order(p, 1, 1)
+    assert ei.value.status == hb.E_PATTERN
+
+
+def test_graph_create_rejects_bad_offsets_on_host():
+    lib = hpm.load()
+    h = ctypes.c_void_p()
+    nb = np.array([1, 0], dtype=np.int32)
+    for off in ([0, 1, 0], [1, 1, 2], [0, 3, 2], [0, 1, 3]):
+        o = np.array(off, dtype=np.int64)
+        st = lib.hpm_graph_create(ctypes.byref(h), 2, 2, o.ctypes.data, nb.ctypes.data,
+                                  o.ctypes.data, nb.ctypes.data, 0, None, 0, None, None)
+        assert st == hb.E_GRAPH, off
+    o = np.array([0, 1, 2], dtype=np.int64)
+    assert lib.hpm_graph_create(None, 2, 2, o.ctypes.data, nb.ctypes.data, o.ctypes.data,
+                                nb.ctypes.data, 0, None, 0, None, None) == hb.E_ARG
+    assert lib.hpm_graph_create(ctypes.byref(h), 2, 1 << 31, o.ctypes.data, nb.ctypes.data,
+                                o.ctypes.data, nb.ctypes.data, 0, None, 0, None,
+                                None) == hb.E_UNSUPPORTED
+    assert lib.hpm_graph_create(ctypes.byref(h), 2, 2, o.ctypes.data, nb.ctypes.data,
+                                o.ctypes.data, nb.ctypes.data, 5, None, 0, None,
+                                None) == hb.E_ARG
+
+
+def test_match_rejects_null_arguments():
+    lib = hpm.load()
+    cnt = ctypes.c_uint64()
+    p, keep = hb._pattern_struct(motif("cycle3"))
+    assert lib.hpm_match(None, ctypes.byref(p), 0, None, None, ctypes.byref(cnt), None,
+                         0) == hb.E_ARG
+
+
+def test_motif_orders_are_valid():
+    for name, (k, arcs) in MOTIFS.items():
+        p = make_pattern(k, arcs, 1, 1)
+        assert is_weakly_connected(k, arcs)
+        _check_order(p, hpm.plan_order(p, 1, 1))
