@@ -112,7 +112,7 @@ def test_rmat_motifs(scale):
 
 
 def test_unlabelled_rmat_4_vertex_motifs():
-    g = rmat(11, 1 << 14, seed=31)
+    g = rmat(10, 1 << 13, seed=31)
     dg = hpm.Graph.from_host(g)
     for name in ("cycle4", "ffl_tail", "star3_back", "clique4_minus1", "cycle3"):
         p = motif(name)
@@ -125,11 +125,16 @@ def test_five_vertex_motifs_connectome_shape():
     from synth.graphs import connectome
     g = connectome(30_000, 240_000, seed=8)
     dg = hpm.Graph.from_host(g)
+    rng = np.random.default_rng(0)
     for name in configs.C3_MOTIFS:
-        p = motif(name, elabels=[3] * len(MOTIFS[name][1]), eop=GE)
-        for mode in (ISO, MONO):
-            say(f"connectome {name} {mode}")
-            assert_parity(g, dg, p, mode, name)
+        k, arcs = MOTIFS[name]
+        vl = rng.integers(0, 8, size=k).tolist()
+        cases = [motif(name, vlabels=vl, elabels=[3] * len(arcs), eop=GE),
+                 motif(name, elabels=[10] * len(arcs), eop=GE)]
+        for p in cases:
+            for mode in (ISO, MONO):
+                say(f"connectome {name} labels={p.vval.ravel().tolist()} mode={mode}")
+                assert_parity(g, dg, p, mode, name)
 
 
 def test_two_vertex_patterns():
@@ -158,23 +163,30 @@ def test_random_patterns_up_to_eight_vertices():
 
 
 def test_largest_pattern_sixteen_vertices():
-    # 16-vertex directed path on a dense small graph (all labels equal)
-    A = (np.random.default_rng(3).random((20, 20)) < 0.35).astype(np.int64)
-    np.fill_diagonal(A, 0)
-    g = from_dense(A, [np.zeros(20)], [np.zeros((20, 20))])
+    # directed 48-cycle plus sparse random chords; 16-vertex patterns
+    rng = np.random.default_rng(3)
+    n = 48
+    A = np.zeros((n, n), dtype=np.int64)
+    A[np.arange(n), (np.arange(n) + 1) % n] = 1
+    R = (rng.random((n, n)) < 0.04).astype(np.int64)
+    np.fill_diagonal(R, 0)
+    A = np.maximum(A, R)
+    g = from_dense(A, [rng.integers(0, 2, size=n)], [np.zeros((n, n))])
     dg = hpm.Graph.from_host(g)
-    p = make_pattern(16, [(i, i + 1) for i in range(15)], 1, 1)
-    want = oracle.match(g, p, MONO, threads=8, rows=False)
-    got, _ = hpm.match(dg, p, MONO)
-    assert got == want.count
-    pi = make_pattern(6, [(i, i + 1) for i in range(5)], 1, 1)
-    assert_parity(g, dg, pi, ISO, "path6 iso")
+    path = make_pattern(16, [(i, i + 1) for i in range(15)], 1, 1)
+    assert assert_parity(g, dg, path, ISO, "path16 iso") > 0
+    closed = make_pattern(16, [(i, i + 1) for i in range(15)] + [(15, 0), (3, 9)], 1, 1)
+    assert assert_parity(g, dg, closed, MONO, "path16+2 mono") > 0
 
 
 def test_reorder_and_budget_invariance():
-    g = configs.c2_graph(scale=12)
-    dg = hpm.Graph.from_host(g)
-    for p, mode in configs.c2_runs():
+    g12 = configs.c2_graph(scale=12)
+    g11 = rmat(11, 1 << 14, seed=31)
+    cases = [(g12, p, mode) for p, mode in configs.c2_runs()]
+    cases += [(g11, motif(name), ISO) for name in ("cycle4", "ffl_tail", "clique4_minus1")]
+    devs = {}
+    for g, p, mode in cases:
+        dg = devs.setdefault(id(g), hpm.Graph.from_host(g))
         base_cnt, base = gpu_rows(dg, p, mode)
         c1, r1 = gpu_rows(dg, p, mode, flags=hpm.F_NO_REORDER)
         assert c1 == base_cnt
