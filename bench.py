@@ -195,6 +195,11 @@ def main():
         "edge_scan_gbs": scan_gbs,
         "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in fam_ms.items()},
         "counts": counts,
+        "per_query": [{"query": f"{p.name}/{'iso' if mode == 0 else 'mono'}", "count": st["count"],
+                       "survivors": st["survivors"], "rows": st["rows"][2:p.k],
+                       "work": st["work"][2:p.k],
+                       "kernel_ms": {k: round(v, 4) for k, v in st["kernel_ms"].items() if v}}
+                      for st, (p, mode) in zip(all_stats[-len(runs):], runs)],
         "roofline": roofline,
     }
     if args.cpu_baseline:

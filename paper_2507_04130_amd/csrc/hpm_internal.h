@@ -18,6 +18,14 @@ constexpr int kExpandItems = 4;       // candidates per thread per tile in the e
 constexpr int kExpandTile = kBlock * kExpandItems;
 constexpr int kPivotItems = 4;        // rows per thread in the pivot/length pass
 constexpr int kPivotTile = kBlock * kPivotItems;
+constexpr int kLdsRowInts = 1024;     // partial-mapping entries staged in LDS per tile
+constexpr int kTilePool = 2048;       // LDS entries for staged adjacency lists per block
+constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront stages
+constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
+
+// Per-vertex validator flags: bit p set when the vertex may be the image of
+// pattern position p (k <= 16 positions).
+using vflag_t = uint16_t;
 
 // Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.
 struct DevGraph {
@@ -76,27 +84,28 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
                                 const int32_t* out_nbrs, int32_t n, int32_t m, int32_t* in_eid,
                                 uint32_t* err, hipStream_t stream);
 
-hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint8_t* vflag,
+hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
                                    hipStream_t stream);
 // out_mode: 0 write depth-2 rows [.][2] in position order; 1 count only;
 // 2 write final rows [.][2] in original pattern order (two-vertex patterns).
-hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint8_t* vflag,
+hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
                             int32_t e_begin, int32_t e_end, int out_mode, int32_t* out,
                             unsigned long long* cursor, unsigned long long out_cap,
                             int grid, hipStream_t stream);
-// Pivot choice and candidate-list length of every row at depth d; writes piv[r],
-// len into off[0..r) and per-block sums into bsum[ceil(r / kPivotTile)].
+// Pivot choice and candidate-list length of every row at depth d; writes piv[r]
+// ({code, list start}), len into off[0..r) and per-block sums into
+// bsum[ceil(r / kPivotTile)].
 hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
-                            const int32_t* rows, int32_t r, int32_t* piv, int64_t* off,
+                            const int32_t* rows, int32_t r, int2* piv, int64_t* off,
                             int64_t* bsum, hipStream_t stream);
 // Turns the lengths in off[0..r) into exclusive prefix sums; off[r] = total.
 hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream_t stream);
 // out_mode: 0 write depth d+1 rows; 1 count only; 2 count and write final rows.
-hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, int32_t d, const int32_t* rows,
-                         const int64_t* off, const int32_t* piv, int32_t r, int64_t w_begin,
-                         int64_t w_end, int out_mode, int32_t* out, unsigned long long* cursor,
-                         unsigned long long out_cap, unsigned long long* partials, int grid,
-                         hipStream_t stream);
+hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
+                         const int32_t* rows, const int64_t* off, const int2* piv, int32_t r,
+                         int64_t w_begin, int64_t w_end, int out_mode, int32_t* out,
+                         unsigned long long* cursor, unsigned long long out_cap,
+                         unsigned long long* partials, int grid, hipStream_t stream);
 // total[0] += sum(partials[0..nparts)); overflow[0] |= 1 on uint64 wrap.
 hipError_t launch_reduce_counts(const unsigned long long* partials, int32_t nparts,
                                 unsigned long long* total, uint32_t* overflow, hipStream_t stream);

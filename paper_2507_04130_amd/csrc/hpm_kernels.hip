@@ -1,9 +1,8 @@
 // hpm_kernels.hip -- device side of libhpm (gfx950, wave64).
 //
 // Kernels, in the order a match runs them:
-//   k_vertex_validator  vertex validator for pattern positions 0 and 1
-//                       (Sec. III-B, Alg. 2; position 1 gets the same test,
-//                       which is the degree part of Alg. 3)
+//   k_vertex_validator  vertex validator (Sec. III-B, Alg. 2) evaluated for
+//                       every pattern position: one flag word per vertex
 //   k_edge_scan         every target arc as a candidate image of pattern arc
 //                       (0,1): vertex flags, arc attributes, reverse arc
 //                       (Sec. III-B, Alg. 3; Sec. III-C, Alg. 4), compacted
@@ -70,6 +69,46 @@ __device__ __forceinline__ int32_t find_in(const int32_t* __restrict__ a, int32_
       h = mid;
   }
   return (l < hi && a[l] == key) ? l : -1;
+}
+
+// Orders LDS traffic of one wavefront (a compiler barrier plus wave-scope fences).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Index of key in the ascending LDS run a[0, len), or -1.
+__device__ __forceinline__ int32_t lds_find(const int32_t* a, int32_t len, int32_t key) {
+  int32_t l = 0, h = len;
+  while (l < h) {
+    const int32_t mid = (l + h) >> 1;
+    if (a[mid] < key)
+      l = mid + 1;
+    else
+      h = mid;
+  }
+  return (l < len && a[l] == key) ? l : -1;
+}
+
+// Position of key in the ascending run a[lo, hi), or -1.  Must be called by the
+// whole wavefront with the same lo and hi.  A run of at most kWaveList entries
+// is copied into the wavefront's LDS buffer wl with coalesced loads and each
+// lane binary-searches it there; a longer run is searched in global memory.
+// Lanes with active == false take part in the copy and return -1.
+__device__ __forceinline__ int32_t wave_member(const int32_t* __restrict__ a, int32_t lo,
+                                               int32_t hi, int32_t key, bool active,
+                                               int32_t* wl, int lane) {
+  const int32_t len = hi - lo;
+  if (len <= kWaveList) {
+    wave_sync();  // earlier readers of wl are done
+    for (int32_t t = lane; t < len; t += 64) wl[t] = a[lo + t];
+    wave_sync();
+    if (!active) return -1;
+    const int32_t x = lds_find(wl, len, key);
+    return x >= 0 ? lo + x : -1;
+  }
+  return active ? find_in(a, lo, hi, key) : -1;
 }
 
 // Block-wide exclusive scan of one value per thread; *total gets the sum.
@@ -181,17 +220,31 @@ __global__ __launch_bounds__(kBlock) void k_transpose_ids(
 
 __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
                                                              const DevPlan* __restrict__ P,
-                                                             uint8_t* __restrict__ vflag) {
-  const int32_t pin0 = P->pin[0], pout0 = P->pout[0];
-  const int32_t pin1 = P->pin[1], pout1 = P->pout[1];
+                                                             vflag_t* __restrict__ vflag) {
+  // Bit p of vflag[v]: v passes the vertex validator for pattern position p
+  // (predicates and in/out degree at least the pattern's).  Alg. 2 states it
+  // for position 0 and Alg. 3 applies it to position 1; the same test is a
+  // sound filter for every later position, so it is computed once per vertex.
+  const int32_t k = P->k;
+  uint32_t cols = 0;
+  for (int p = 0; p < k; ++p) cols |= P->vmask[p];
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n;
        v += (int64_t)gridDim.x * kBlock) {
     const int32_t dout = g.out_off[v + 1] - g.out_off[v];
     const int32_t din = g.in_off[v + 1] - g.in_off[v];
-    uint8_t f = 0;
-    if (din >= pin0 && dout >= pout0 && vertex_ok(g, P, 0, (int32_t)v)) f |= 1;
-    if (din >= pin1 && dout >= pout1 && vertex_ok(g, P, 1, (int32_t)v)) f |= 2;
-    vflag[v] = f;
+    int32_t x[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) x[c] = ((cols >> c) & 1u) ? g.vcol[c][v] : 0;
+    uint32_t f = 0;
+    for (int p = 0; p < k; ++p) {
+      bool ok = din >= P->pin[p] && dout >= P->pout[p];
+      const uint32_t mask = P->vmask[p];
+#pragma unroll
+      for (int c = 0; c < kMaxCols; ++c)
+        if ((mask >> c) & 1u) ok = ok && x[c] >= P->vlo[p][c] && x[c] <= P->vhi[p][c];
+      f |= (uint32_t)ok << p;
+    }
+    vflag[v] = (vflag_t)f;
   }
 }
 
@@ -199,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
 
 template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan* __restrict__ P,
-                                                      const uint8_t* __restrict__ vflag,
+                                                      const vflag_t* __restrict__ vflag,
                                                       int32_t e_begin, int32_t e_end,
                                                       int32_t* __restrict__ out,
                                                       unsigned long long* __restrict__ cursor,
@@ -281,9 +334,13 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
 
 __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan* __restrict__ P,
                                                       int32_t d, const int32_t* __restrict__ rows,
-                                                      int32_t r, int32_t* __restrict__ piv,
+                                                      int32_t r, int2* __restrict__ piv,
                                                       int64_t* __restrict__ len,
                                                       int64_t* __restrict__ bsum) {
+  // For row i (a partial mapping of positions 0..d-1) pick, among the mapped
+  // pattern neighbours b of position d, the adjacency list of f(b) in the
+  // arc's direction with the fewest entries: every image of position d lies in
+  // it.  piv[i] = {(b << 1) | via_out, first index of that list}.
   __shared__ int64_t s_scan[kWaves + 1];
   const uint32_t fw = P->fwd[d], bw = P->bwd[d];
   int64_t sum = 0;
@@ -291,22 +348,24 @@ __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan*
   for (int it = 0; it < kPivotItems; ++it) {
     const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
     if (i < r) {
-      int32_t best = INT32_MAX, code = 0;
+      int32_t best = INT32_MAX, code = 0, base = 0;
       for (int b = 0; b < d; ++b) {
         if (((fw | bw) >> b) & 1u) {
           const int32_t fb = rows[i * d + b];
           if ((fw >> b) & 1u) {
-            const int32_t L = g.out_off[fb + 1] - g.out_off[fb];
-            if (L < best) { best = L; code = (b << 1) | 1; }
+            const int32_t lo = g.out_off[fb];
+            const int32_t L = g.out_off[fb + 1] - lo;
+            if (L < best) { best = L; code = (b << 1) | 1; base = lo; }
           }
           if ((bw >> b) & 1u) {
-            const int32_t L = g.in_off[fb + 1] - g.in_off[fb];
-            if (L < best) { best = L; code = b << 1; }
+            const int32_t lo = g.in_off[fb];
+            const int32_t L = g.in_off[fb + 1] - lo;
+            if (L < best) { best = L; code = b << 1; base = lo; }
           }
         }
       }
       if (best == INT32_MAX) best = 0;  // cannot happen: every position has an earlier neighbour
-      piv[i] = code;
+      piv[i] = make_int2(code, base);
       len[i] = best;
       sum += best;
     }
@@ -355,26 +414,53 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int64_t* __restrict__ off
   }
 }
 
+// One checked relation of the position being filled, packed as
+// q | dir << 5 | required << 6: dir 0 is the pattern arc q -> a (target arc
+// f(q) -> c, looked up in out(f(q))), dir 1 the arc a -> q (c -> f(q), looked
+// up in in(f(q))); required 0 means the arc is absent in the pattern and must
+// be absent in the target (induced isomorphism only).
+__device__ __forceinline__ int32_t pack_cons(int q, int dir, int req) {
+  return q | (dir << 5) | (req << 6);
+}
+
 template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_expand(
-    DevGraph g, const DevPlan* __restrict__ P, int32_t d, const int32_t* __restrict__ rows,
-    const int64_t* __restrict__ off, const int32_t* __restrict__ piv, int32_t r, int64_t w_begin,
-    int64_t w_end, int32_t* __restrict__ out, unsigned long long* __restrict__ cursor,
-    unsigned long long out_cap, unsigned long long* __restrict__ partials) {
+    DevGraph g, const DevPlan* __restrict__ P, const vflag_t* __restrict__ vflag, int32_t d,
+    const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
+    const int2* __restrict__ piv, int32_t r, int64_t w_begin, int64_t w_end,
+    int32_t* __restrict__ out, unsigned long long* __restrict__ cursor, unsigned long long out_cap,
+    unsigned long long* __restrict__ partials) {
+  // Work item w in [w_begin, w_end) is candidate j = w - off[i] of the row i
+  // with off[i] <= w < off[i+1]: entry j of that row's pivot list.  A tile of
+  // kExpandTile consecutive items covers rows [r_lo, r_hi]; their prefix sums,
+  // pivots and (if small) the rows themselves are staged in LDS.
+  //
+  // Membership tests (is f(q) -> c an arc?) go three ways:
+  //  * tile inside one row (long pivot lists): the tile's candidates are the
+  //    sorted run [cmin, cmax] of one list, so every checked list is cut to
+  //    that window once per tile and the windows are staged in LDS;
+  //  * wavefront inside one row: checked lists of at most kWaveList entries
+  //    are staged in the wavefront's LDS slice;
+  //  * otherwise each lane binary-searches the list of the mapped vertex.
   __shared__ int64_t s_off[kExpandTile + 1];
-  __shared__ int32_t s_rng[2];
+  __shared__ int2 s_piv[kExpandTile];
+  __shared__ int32_t s_rows[kLdsRowInts];
+  __shared__ int32_t s_pool[kTilePool];
+  __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
+  __shared__ int32_t s_misc[5];
   __shared__ unsigned long long s_scan[kWaves + 1];
   __shared__ unsigned long long s_base;
   const int32_t a = d;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
   const bool iso = P->mode == 0;
-  const int32_t pin_a = P->pin[a], pout_a = P->pout[a];
   const int32_t k = P->k;
+  const int lane = threadIdx.x & 63;
+  int32_t* wl = s_pool + (threadIdx.x >> 6) * kWaveList;
   unsigned long long my_count = 0;
   const int64_t ntiles = (w_end - w_begin + kExpandTile - 1) / kExpandTile;
   for (int64_t t = xcd_block_id(); t < ntiles; t += gridDim.x) {
     const int64_t tb = w_begin + t * kExpandTile;
-    const int64_t te = min(tb + (int64_t)kExpandTile, w_end);
+    const int64_t te = (tb + kExpandTile < w_end) ? tb + kExpandTile : w_end;
     if (threadIdx.x < 2) {
       // last row i in [0, r) with off[i] <= key
       const int64_t key = threadIdx.x == 0 ? tb : te - 1;
@@ -386,96 +472,232 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         else
           hi = mid - 1;
       }
-      s_rng[threadIdx.x] = lo;
+      s_misc[threadIdx.x] = lo;
     }
     __syncthreads();
-    const int32_t r_lo = s_rng[0], r_hi = s_rng[1];
+    const int32_t r_lo = s_misc[0], r_hi = s_misc[1];
     const int32_t nrow = r_hi - r_lo + 1;
+    const bool single = nrow == 1;
     const bool use_lds = nrow <= kExpandTile;
-    if (use_lds)
+    const bool rows_lds = use_lds && nrow * d <= kLdsRowInts;
+    if (use_lds) {
       for (int32_t i = threadIdx.x; i <= nrow; i += kBlock) s_off[i] = off[r_lo + i];
+      for (int32_t i = threadIdx.x; i < nrow; i += kBlock) s_piv[i] = piv[r_lo + i];
+      if (rows_lds)
+        for (int32_t i = threadIdx.x; i < nrow * d; i += kBlock)
+          s_rows[i] = rows[(int64_t)r_lo * d + i];
+    }
+    if (single && threadIdx.x == 0) {
+      const int2 pv = piv[r_lo];
+      const int32_t b = pv.x >> 1;
+      const bool vo = (pv.x & 1) != 0;
+      int32_t n = 0;
+      for (int q = 0; q < d; ++q) {
+        const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
+        if (arc_in ? !(q == b && vo) : iso) s_cons[n++] = pack_cons(q, 0, arc_in);
+        if (arc_out ? !(q == b && !vo) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);
+      }
+      s_misc[2] = n;
+      const int64_t o = off[r_lo];
+      const int32_t* list = vo ? g.out_nbrs : g.in_nbrs;
+      s_misc[3] = list[pv.y + (int32_t)(tb - o)];
+      s_misc[4] = list[pv.y + (int32_t)(te - 1 - o)];
+    }
     __syncthreads();
+    int32_t ncons = 0;
+    if (single) {
+      ncons = s_misc[2];
+      if ((int32_t)threadIdx.x < 2 * ncons) {
+        // two threads per relation: lower end of cmin, upper end of cmax
+        const int32_t ci = threadIdx.x >> 1;
+        const int32_t desc = s_cons[ci];
+        const int32_t fq = rows[(int64_t)r_lo * d + (desc & 31)];
+        const bool in_dir = ((desc >> 5) & 1) != 0;
+        const int32_t* lst = in_dir ? g.in_nbrs : g.out_nbrs;
+        int32_t l = in_dir ? g.in_off[fq] : g.out_off[fq];
+        int32_t h = in_dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+        if ((threadIdx.x & 1) == 0) {
+          const int32_t cmin = s_misc[3];
+          while (l < h) {
+            const int32_t mid = l + ((h - l) >> 1);
+            if (lst[mid] < cmin)
+              l = mid + 1;
+            else
+              h = mid;
+          }
+          s_wlo[ci] = l;
+        } else {
+          const int32_t cmax = s_misc[4];
+          while (l < h) {
+            const int32_t mid = l + ((h - l) >> 1);
+            if (lst[mid] <= cmax)
+              l = mid + 1;
+            else
+              h = mid;
+          }
+          s_whi[ci] = l;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int32_t ci = 0; ci < ncons; ++ci) {
+          const int32_t len = s_whi[ci] - s_wlo[ci];
+          if (acc + len <= kTilePool) {
+            s_woff[ci] = acc;
+            acc += len;
+          } else {
+            s_woff[ci] = -1;
+          }
+        }
+      }
+      __syncthreads();
+      for (int32_t ci = 0; ci < ncons; ++ci) {
+        const int32_t woff = s_woff[ci];
+        if (woff < 0) continue;
+        const int32_t* lst = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
+        const int32_t lo = s_wlo[ci], len = s_whi[ci] - lo;
+        for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = lst[lo + x];
+      }
+      __syncthreads();
+    }
 
     int32_t cand[kExpandItems], crow[kExpandItems];
     uint32_t keep = 0;
 #pragma unroll
     for (int it = 0; it < kExpandItems; ++it) {
+      // Items of one wavefront are 64 consecutive w, so valid lanes form a prefix.
       const int64_t w = tb + it * kBlock + threadIdx.x;
-      cand[it] = 0;
-      crow[it] = 0;
-      if (w >= te) continue;
-      int32_t i;
-      int64_t oi;
-      if (use_lds) {
-        int32_t lo = 0, hi = nrow - 1;
-        while (lo < hi) {
-          const int32_t mid = lo + ((hi - lo + 1) >> 1);
-          if (s_off[mid] <= w)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        i = r_lo + lo;
-        oi = s_off[lo];
-      } else {
-        int32_t lo = r_lo, hi = r_hi;
-        while (lo < hi) {
-          const int32_t mid = lo + ((hi - lo + 1) >> 1);
-          if (off[mid] <= w)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        i = lo;
-        oi = off[lo];
-      }
-      const int32_t j = (int32_t)(w - oi);
-      const int32_t code = piv[i];
-      const int32_t b = code >> 1;
-      const bool via_out = (code & 1) != 0;
-      const int32_t* row = rows + (int64_t)i * d;
-      const int32_t fb = row[b];
-      int32_t c, eid;
-      if (via_out) {
-        const int32_t base = g.out_off[fb];
-        c = g.out_nbrs[base + j];
-        eid = base + j;
-      } else {
-        const int32_t base = g.in_off[fb];
-        c = g.in_nbrs[base + j];
-        eid = g.in_eid[base + j];
-      }
-      bool ok = via_out ? arc_ok(g, P, b, a, eid) : arc_ok(g, P, a, b, eid);
-      for (int q = 0; q < d && ok; ++q) ok = row[q] != c;  // injectivity
-      if (ok) {
-        const int32_t dout = g.out_off[c + 1] - g.out_off[c];
-        const int32_t din = g.in_off[c + 1] - g.in_off[c];
-        ok = din >= pin_a && dout >= pout_a && vertex_ok(g, P, a, c);
-      }
-      for (int q = 0; q < d && ok; ++q) {
-        const int32_t fq = row[q];
-        // pattern arc q -> a  <=>  target arc f(q) -> c  (=> only, for monomorphism)
-        if ((fw >> q) & 1u) {
-          if (!(q == b && via_out)) {
-            const int32_t pos = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
-            ok = pos >= 0 && arc_ok(g, P, q, a, pos);
+      const bool valid = w < te;
+      int32_t i = r_lo, li = 0, c = 0, b = 0, pos = 0;
+      bool via_out = false;
+      if (valid) {
+        int64_t oi;
+        int2 pv;
+        if (use_lds) {
+          int32_t lo = 0, hi = nrow - 1;
+          while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo + 1) >> 1);
+            if (s_off[mid] <= w)
+              lo = mid;
+            else
+              hi = mid - 1;
           }
-        } else if (iso) {
-          ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
-        }
-        if (!ok) break;
-        // pattern arc a -> q  <=>  target arc c -> f(q)
-        if ((bw >> q) & 1u) {
-          if (!(q == b && !via_out)) {
-            const int32_t pos = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
-            ok = pos >= 0 && arc_ok(g, P, a, q, g.in_eid[pos]);
+          li = lo;
+          i = r_lo + lo;
+          oi = s_off[lo];
+          pv = s_piv[lo];
+        } else {
+          int32_t lo = r_lo, hi = r_hi;
+          while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo + 1) >> 1);
+            if (off[mid] <= w)
+              lo = mid;
+            else
+              hi = mid - 1;
           }
-        } else if (iso) {
-          ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
+          i = lo;
+          oi = off[lo];
+          pv = piv[lo];
         }
+        b = pv.x >> 1;
+        via_out = (pv.x & 1) != 0;
+        pos = pv.y + (int32_t)(w - oi);
+        c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
       }
       cand[it] = c;
       crow[it] = i;
+      const uint64_t vmask = __ballot(valid);
+      if (vmask == 0) continue;  // wave-uniform
+      const int32_t* grow = rows + (int64_t)i * d;
+      const int32_t* lrow = s_rows + li * d;
+      auto rowv = [&](int q) -> int32_t { return rows_lds ? lrow[q] : grow[q]; };
+
+      // vertex validator for position a (predicates, degrees)
+      bool ok = valid && ((vflag[c] >> a) & 1u) != 0;
+      // predicate of the pivot arc itself
+      if (ok) {
+        if (via_out) {
+          if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
+        } else if (P->amask[a][b]) {
+          ok = arc_ok(g, P, a, b, g.in_eid[pos]);
+        }
+      }
+      for (int q = 0; q < d && ok; ++q) ok = rowv(q) != c;  // injectivity
+
+      if (single) {
+        for (int32_t ci = 0; ci < ncons; ++ci) {
+          if (!__any(ok)) break;  // wave-uniform
+          if (!ok) continue;
+          const int32_t desc = s_cons[ci];
+          const int q = desc & 31;
+          const bool in_dir = ((desc >> 5) & 1) != 0;
+          const bool req = ((desc >> 6) & 1) != 0;
+          const int32_t wlo = s_wlo[ci], whi = s_whi[ci], woff = s_woff[ci];
+          int32_t p;
+          if (woff >= 0) {
+            const int32_t x = lds_find(s_pool + woff, whi - wlo, c);
+            p = x >= 0 ? wlo + x : -1;
+          } else {
+            p = find_in(in_dir ? g.in_nbrs : g.out_nbrs, wlo, whi, c);
+          }
+          if (!req) {
+            ok = p < 0;
+          } else if (!in_dir) {
+            ok = p >= 0 && arc_ok(g, P, q, a, p);
+          } else {
+            ok = p >= 0 && (!P->amask[a][q] || arc_ok(g, P, a, q, g.in_eid[p]));
+          }
+        }
+      } else {
+        // Does the whole wavefront extend one row?  Then all lanes probe the
+        // same lists, and short ones are staged once in LDS (wave_member).
+        const int32_t i0 = __shfl(i, 0);
+        const bool same_row = __ballot(valid && i == i0) == vmask;
+        if (same_row) {
+          const int32_t b0 = __shfl(b, 0);
+          const bool vo0 = __shfl((int)via_out, 0) != 0;
+          for (int q = 0; q < d; ++q) {
+            if (!__any(ok)) break;  // wave-uniform
+            const int32_t fq = __shfl(rowv(q), 0);
+            const bool arc_in = (fw >> q) & 1u;   // pattern arc q -> a
+            const bool arc_out = (bw >> q) & 1u;  // pattern arc a -> q
+            if (arc_in ? !(q == b0 && vo0) : iso) {
+              const int32_t e =
+                  wave_member(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c, ok, wl, lane);
+              if (ok) ok = arc_in ? (e >= 0 && arc_ok(g, P, q, a, e)) : e < 0;
+            }
+            if (arc_out ? !(q == b0 && !vo0) : iso) {
+              const int32_t e =
+                  wave_member(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c, ok, wl, lane);
+              if (ok) ok = arc_out ? (e >= 0 && arc_ok(g, P, a, q, g.in_eid[e])) : e < 0;
+            }
+          }
+        } else {
+          for (int q = 0; q < d && ok; ++q) {
+            const int32_t fq = rowv(q);
+            // pattern arc q -> a  <=>  target arc f(q) -> c  (=> only, for monomorphism)
+            if ((fw >> q) & 1u) {
+              if (!(q == b && via_out)) {
+                const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
+                ok = e >= 0 && arc_ok(g, P, q, a, e);
+              }
+            } else if (iso) {
+              ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
+            }
+            if (!ok) break;
+            // pattern arc a -> q  <=>  target arc c -> f(q)
+            if ((bw >> q) & 1u) {
+              if (!(q == b && !via_out)) {
+                const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
+                ok = e >= 0 && arc_ok(g, P, a, q, g.in_eid[e]);
+              }
+            } else if (iso) {
+              ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
+            }
+          }
+        }
+      }
       keep |= (uint32_t)ok << it;
     }
 
@@ -508,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       }
       if (OUT == 2) my_count += cnt;
     }
-    __syncthreads();  // s_off, s_rng and s_base are rewritten by the next tile
+    __syncthreads();  // LDS staging and s_base are rewritten by the next tile
   }
   if (OUT != 0) {
     const unsigned long long tot = block_sum<unsigned long long>(my_count, s_scan);
@@ -584,7 +806,7 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
   return hipGetLastError();
 }
 
-hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint8_t* vflag,
+hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
                                    hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
   k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan,
@@ -592,7 +814,7 @@ hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint8
   return hipGetLastError();
 }
 
-hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint8_t* vflag,
+hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
                             int32_t e_begin, int32_t e_end, int out_mode, int32_t* out,
                             unsigned long long* cursor, unsigned long long out_cap, int grid,
                             hipStream_t stream) {
@@ -615,7 +837,7 @@ hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint8_
 }
 
 hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
-                            const int32_t* rows, int32_t r, int32_t* piv, int64_t* off,
+                            const int32_t* rows, int32_t r, int2* piv, int64_t* off,
                             int64_t* bsum, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
   const int nb = (int)(((int64_t)r + kPivotTile - 1) / kPivotTile);
@@ -633,24 +855,24 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, int32_t d, const int32_t* rows,
-                         const int64_t* off, const int32_t* piv, int32_t r, int64_t w_begin,
-                         int64_t w_end, int out_mode, int32_t* out, unsigned long long* cursor,
-                         unsigned long long out_cap, unsigned long long* partials, int grid,
-                         hipStream_t stream) {
+hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
+                         const int32_t* rows, const int64_t* off, const int2* piv, int32_t r,
+                         int64_t w_begin, int64_t w_end, int out_mode, int32_t* out,
+                         unsigned long long* cursor, unsigned long long out_cap,
+                         unsigned long long* partials, int grid, hipStream_t stream) {
   if (w_end <= w_begin || r <= 0) return hipSuccess;
   switch (out_mode) {
     case 0:
-      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, d, rows, off, piv, r, w_begin, w_end, out,
-                                               cursor, out_cap, partials);
+      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
+                                               w_end, out, cursor, out_cap, partials);
       break;
     case 1:
-      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, d, rows, off, piv, r, w_begin, w_end, out,
-                                               cursor, out_cap, partials);
+      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
+                                               w_end, out, cursor, out_cap, partials);
       break;
     default:
-      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, d, rows, off, piv, r, w_begin, w_end, out,
-                                               cursor, out_cap, partials);
+      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
+                                               w_end, out, cursor, out_cap, partials);
       break;
   }
   return hipGetLastError();

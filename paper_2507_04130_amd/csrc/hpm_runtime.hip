@@ -456,7 +456,7 @@ struct Matcher {
   void ensure_depth(int32_t d, int64_t r_cap) {
     const int64_t nb = (r_cap + hpm::kPivotTile - 1) / hpm::kPivotTile;
     W->off[d].ensure((size_t)(r_cap + 1) * sizeof(int64_t), stream);
-    W->piv[d].ensure((size_t)std::max<int64_t>(r_cap, 1) * sizeof(int32_t), stream);
+    W->piv[d].ensure((size_t)std::max<int64_t>(r_cap, 1) * sizeof(int2), stream);
     W->bsum[d].ensure((size_t)(nb + 1) * sizeof(int64_t), stream);
   }
 
@@ -465,7 +465,7 @@ struct Matcher {
     if (r == 0) return;
     st.rows[d] += r;
     int64_t* off = W->off[d].as<int64_t>();
-    int32_t* piv = W->piv[d].as<int32_t>();
+    int2* piv = W->piv[d].as<int2>();
     int64_t* bsum = W->bsum[d].as<int64_t>();
     launch(HPM_K_ROW_PIVOT, [&] {
       return hpm::launch_row_pivot(g, dplan(), d, rows, (int32_t)r, piv, off, bsum, stream);
@@ -478,7 +478,8 @@ struct Matcher {
       const int grid = grid_for(work, hpm::kExpandTile);
       const int mode = maps ? 2 : 1;
       launch(HPM_K_LAST_LEVEL, [&] {
-        return hpm::launch_expand(g, dplan(), d, rows, off, piv, (int32_t)r, 0, work, mode, maps,
+        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, off, piv,
+                                  (int32_t)r, 0, work, mode, maps,
                                   counters() + kCntEmit, maps ? cap : 0,
                                   W->partials.as<unsigned long long>(), grid, stream);
       });
@@ -500,7 +501,8 @@ struct Matcher {
       zero_counter(kCntCursor);
       const int grid = grid_for(n_items, hpm::kExpandTile);
       launch(HPM_K_EXPAND, [&] {
-        return hpm::launch_expand(g, dplan(), d, rows, off, piv, (int32_t)r, w0, w1, 0, out,
+        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, off, piv,
+                                  (int32_t)r, w0, w1, 0, out,
                                   counters() + kCntCursor, (unsigned long long)n_items,
                                   W->partials.as<unsigned long long>(), grid, stream);
       });
@@ -514,13 +516,13 @@ struct Matcher {
     const int64_t m = G->m;
     st.arcs_scanned = (uint64_t)m;
     launch(HPM_K_VERTEX_VALIDATOR, [&] {
-      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<uint8_t>(), stream);
+      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<hpm::vflag_t>(), stream);
     });
     if (k == 2) {
       zero_counter(kCntCursor);
       const int grid = grid_for(m, hpm::kScanTile);
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<uint8_t>(), 0, (int32_t)m,
+        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<hpm::vflag_t>(), 0, (int32_t)m,
                                      maps ? 2 : 1, maps, counters() + kCntCursor,
                                      maps ? cap : 0, grid, stream);
       });
@@ -535,7 +537,7 @@ struct Matcher {
       zero_counter(kCntCursor);
       const int grid = grid_for(e1 - e0, hpm::kScanTile);
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<uint8_t>(), (int32_t)e0, (int32_t)e1,
+        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<hpm::vflag_t>(), (int32_t)e0, (int32_t)e1,
                                      0, W->rows2.as<int32_t>(), counters() + kCntCursor,
                                      (unsigned long long)(e1 - e0), grid, stream);
       });
@@ -735,7 +737,7 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     // per-block partial counts.  Depth 2 costs 21 B per row of an arc chunk
     // (row 8, prefix 8, pivot 4, block sums); depth d >= 3 costs 4d + 13 B per row.
     const int max_grid = std::max(64, G->num_cus * 8);
-    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n + 64 +
+    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n * sizeof(hpm::vflag_t) + 64 +
                            (uint64_t)max_grid * sizeof(unsigned long long) + 4096;
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
@@ -790,7 +792,7 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     M.cap2 = cap2;
     M.chunk = chunk;
     W->plan.ensure(sizeof(DevPlan), stream);
-    W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1), stream);
+    W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1) * sizeof(hpm::vflag_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);
     W->partials.ensure((size_t)max_grid * sizeof(unsigned long long), stream);
     if (k >= 3) {
