@@ -78,6 +78,37 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// First x in [lo, hi) with a[x] >= key (upper == false) or a[x] > key
+// (upper == true), hi if none.  Called by all 64 lanes of a wavefront with the
+// same arguments: a 64-ary search, so a list of length L costs about
+// log64(L) + 1 dependent loads instead of log2(L).
+template <typename T>
+__device__ __forceinline__ int32_t wave_bound(const T* __restrict__ a, int32_t lo, int32_t hi,
+                                              T key, bool upper) {
+  const int lane = threadIdx.x & 63;
+  while (hi - lo > 64) {
+    const int32_t step = (hi - lo + 63) >> 6;
+    const int32_t idx = lo + lane * step;
+    bool before = false;
+    if (idx < hi) {
+      const T v = a[idx];
+      before = upper ? (v <= key) : (v < key);
+    }
+    const int cnt = __popcll(__ballot(before));  // the samples before the bound
+    if (cnt == 0) return lo;
+    const int32_t nhi = lo + cnt * step;
+    lo = lo + (cnt - 1) * step + 1;
+    hi = nhi < hi ? nhi : hi;
+  }
+  const int32_t idx = lo + lane;
+  bool before = false;
+  if (idx < hi) {
+    const T v = a[idx];
+    before = upper ? (v <= key) : (v < key);
+  }
+  return lo + __popcll(__ballot(before));
+}
+
 // Index of key in the ascending LDS run a[0, len), or -1.
 __device__ __forceinline__ int32_t lds_find(const int32_t* a, int32_t len, int32_t key) {
   int32_t l = 0, h = len;
@@ -92,13 +123,19 @@ __device__ __forceinline__ int32_t lds_find(const int32_t* a, int32_t len, int32
 }
 
 // Position of key in the ascending run a[lo, hi), or -1.  Must be called by the
-// whole wavefront with the same lo and hi.  A run of at most kWaveList entries
-// is copied into the wavefront's LDS buffer wl with coalesced loads and each
-// lane binary-searches it there; a longer run is searched in global memory.
-// Lanes with active == false take part in the copy and return -1.
+// whole wavefront with the same lo, hi and key window [kmin, kmax] (every
+// active lane's key lies in it).  The run is first cut to the window; if what
+// is left has at most kWaveList entries it is copied into the wavefront's LDS
+// buffer wl with coalesced loads and each lane binary-searches it there,
+// otherwise each lane searches the cut run in global memory.  Lanes with
+// active == false take part in the copy and return -1.
 __device__ __forceinline__ int32_t wave_member(const int32_t* __restrict__ a, int32_t lo,
-                                               int32_t hi, int32_t key, bool active,
-                                               int32_t* wl, int lane) {
+                                               int32_t hi, int32_t key, int32_t kmin,
+                                               int32_t kmax, bool active, int32_t* wl, int lane) {
+  if (hi - lo > kWaveList) {
+    lo = wave_bound<int32_t>(a, lo, hi, kmin, false);
+    hi = wave_bound<int32_t>(a, lo, hi, kmax, true);
+  }
   const int32_t len = hi - lo;
   if (len <= kWaveList) {
     wave_sync();  // earlier readers of wl are done
@@ -461,18 +498,11 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   for (int64_t t = xcd_block_id(); t < ntiles; t += gridDim.x) {
     const int64_t tb = w_begin + t * kExpandTile;
     const int64_t te = (tb + kExpandTile < w_end) ? tb + kExpandTile : w_end;
-    if (threadIdx.x < 2) {
-      // last row i in [0, r) with off[i] <= key
-      const int64_t key = threadIdx.x == 0 ? tb : te - 1;
-      int32_t lo = 0, hi = r - 1;
-      while (lo < hi) {
-        const int32_t mid = lo + ((hi - lo + 1) >> 1);
-        if (off[mid] <= key)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      s_misc[threadIdx.x] = lo;
+    if (threadIdx.x < 128) {
+      // wave 0: first row of the tile, wave 1: last row (last i with off[i] <= key)
+      const int64_t key = threadIdx.x < 64 ? tb : te - 1;
+      const int32_t x = wave_bound<int64_t>(off, 0, r, key, true) - 1;
+      if (lane == 0) s_misc[threadIdx.x >> 6] = x;
     }
     __syncthreads();
     const int32_t r_lo = s_misc[0], r_hi = s_misc[1];
@@ -507,35 +537,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(
     int32_t ncons = 0;
     if (single) {
       ncons = s_misc[2];
-      if ((int32_t)threadIdx.x < 2 * ncons) {
-        // two threads per relation: lower end of cmin, upper end of cmax
-        const int32_t ci = threadIdx.x >> 1;
+      // each wavefront cuts the lists of some relations to [cmin, cmax]
+      for (int32_t ci = threadIdx.x >> 6; ci < ncons; ci += kWaves) {
         const int32_t desc = s_cons[ci];
         const int32_t fq = rows[(int64_t)r_lo * d + (desc & 31)];
         const bool in_dir = ((desc >> 5) & 1) != 0;
         const int32_t* lst = in_dir ? g.in_nbrs : g.out_nbrs;
-        int32_t l = in_dir ? g.in_off[fq] : g.out_off[fq];
-        int32_t h = in_dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
-        if ((threadIdx.x & 1) == 0) {
-          const int32_t cmin = s_misc[3];
-          while (l < h) {
-            const int32_t mid = l + ((h - l) >> 1);
-            if (lst[mid] < cmin)
-              l = mid + 1;
-            else
-              h = mid;
-          }
-          s_wlo[ci] = l;
-        } else {
-          const int32_t cmax = s_misc[4];
-          while (l < h) {
-            const int32_t mid = l + ((h - l) >> 1);
-            if (lst[mid] <= cmax)
-              l = mid + 1;
-            else
-              h = mid;
-          }
-          s_whi[ci] = l;
+        const int32_t l = in_dir ? g.in_off[fq] : g.out_off[fq];
+        const int32_t h = in_dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+        const int32_t wlo = wave_bound<int32_t>(lst, l, h, s_misc[3], false);
+        const int32_t whi = wave_bound<int32_t>(lst, wlo, h, s_misc[4], true);
+        if (lane == 0) {
+          s_wlo[ci] = wlo;
+          s_whi[ci] = whi;
         }
       }
       __syncthreads();
@@ -657,19 +671,21 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         if (same_row) {
           const int32_t b0 = __shfl(b, 0);
           const bool vo0 = __shfl((int)via_out, 0) != 0;
+          const int32_t cmin = __shfl(c, 0);
+          const int32_t cmax = __shfl(c, 63 - __clzll((long long)vmask));
           for (int q = 0; q < d; ++q) {
             if (!__any(ok)) break;  // wave-uniform
             const int32_t fq = __shfl(rowv(q), 0);
             const bool arc_in = (fw >> q) & 1u;   // pattern arc q -> a
             const bool arc_out = (bw >> q) & 1u;  // pattern arc a -> q
             if (arc_in ? !(q == b0 && vo0) : iso) {
-              const int32_t e =
-                  wave_member(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c, ok, wl, lane);
+              const int32_t e = wave_member(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c,
+                                            cmin, cmax, ok, wl, lane);
               if (ok) ok = arc_in ? (e >= 0 && arc_ok(g, P, q, a, e)) : e < 0;
             }
             if (arc_out ? !(q == b0 && !vo0) : iso) {
-              const int32_t e =
-                  wave_member(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c, ok, wl, lane);
+              const int32_t e = wave_member(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c,
+                                            cmin, cmax, ok, wl, lane);
               if (ok) ok = arc_out ? (e >= 0 && arc_ok(g, P, a, q, g.in_eid[e])) : e < 0;
             }
           }
