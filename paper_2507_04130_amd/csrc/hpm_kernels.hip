@@ -460,6 +460,12 @@ __device__ __forceinline__ int32_t pack_cons(int q, int dir, int req) {
   return q | (dir << 5) | (req << 6);
 }
 
+// A single-row tile whose candidate ids lie in [cmin, cmax] checks relations
+// through an LDS bitmap when that range fits in the tile pool.
+__device__ __forceinline__ bool tile_bitmap(int32_t cmin, int32_t cmax) {
+  return (((int64_t)cmax - cmin) >> 5) < kTilePool;
+}
+
 template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_expand(
     DevGraph g, const DevPlan* __restrict__ P, const vflag_t* __restrict__ vflag, int32_t d,
@@ -475,7 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   // Membership tests (is f(q) -> c an arc?) go three ways:
   //  * tile inside one row (long pivot lists): the tile's candidates are the
   //    sorted run [cmin, cmax] of one list, so every checked list is cut to
-  //    that window once per tile and the windows are staged in LDS;
+  //    that window once per tile; the window becomes an LDS bitmap over
+  //    [cmin, cmax] (or, for a wide id range, is staged and binary-searched);
   //  * wavefront inside one row: checked lists of at most kWaveList entries
   //    are staged in the wavefront's LDS slice;
   //  * otherwise each lane binary-searches the list of the mapped vertex.
@@ -553,27 +560,29 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         }
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int32_t acc = 0;
-        for (int32_t ci = 0; ci < ncons; ++ci) {
-          const int32_t len = s_whi[ci] - s_wlo[ci];
-          if (acc + len <= kTilePool) {
-            s_woff[ci] = acc;
-            acc += len;
-          } else {
-            s_woff[ci] = -1;
+      if (!tile_bitmap(s_misc[3], s_misc[4])) {
+        if (threadIdx.x == 0) {
+          int32_t acc = 0;
+          for (int32_t ci = 0; ci < ncons; ++ci) {
+            const int32_t len = s_whi[ci] - s_wlo[ci];
+            if (acc + len <= kTilePool) {
+              s_woff[ci] = acc;
+              acc += len;
+            } else {
+              s_woff[ci] = -1;
+            }
           }
         }
+        __syncthreads();
+        for (int32_t ci = 0; ci < ncons; ++ci) {
+          const int32_t woff = s_woff[ci];
+          if (woff < 0) continue;
+          const int32_t* lst = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
+          const int32_t lo = s_wlo[ci], len = s_whi[ci] - lo;
+          for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = lst[lo + x];
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      for (int32_t ci = 0; ci < ncons; ++ci) {
-        const int32_t woff = s_woff[ci];
-        if (woff < 0) continue;
-        const int32_t* lst = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
-        const int32_t lo = s_wlo[ci], len = s_whi[ci] - lo;
-        for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = lst[lo + x];
-      }
-      __syncthreads();
     }
 
     int32_t cand[kExpandItems], crow[kExpandItems];
@@ -639,31 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       }
       for (int q = 0; q < d && ok; ++q) ok = rowv(q) != c;  // injectivity
 
-      if (single) {
-        for (int32_t ci = 0; ci < ncons; ++ci) {
-          if (!__any(ok)) break;  // wave-uniform
-          if (!ok) continue;
-          const int32_t desc = s_cons[ci];
-          const int q = desc & 31;
-          const bool in_dir = ((desc >> 5) & 1) != 0;
-          const bool req = ((desc >> 6) & 1) != 0;
-          const int32_t wlo = s_wlo[ci], whi = s_whi[ci], woff = s_woff[ci];
-          int32_t p;
-          if (woff >= 0) {
-            const int32_t x = lds_find(s_pool + woff, whi - wlo, c);
-            p = x >= 0 ? wlo + x : -1;
-          } else {
-            p = find_in(in_dir ? g.in_nbrs : g.out_nbrs, wlo, whi, c);
-          }
-          if (!req) {
-            ok = p < 0;
-          } else if (!in_dir) {
-            ok = p >= 0 && arc_ok(g, P, q, a, p);
-          } else {
-            ok = p >= 0 && (!P->amask[a][q] || arc_ok(g, P, a, q, g.in_eid[p]));
-          }
-        }
-      } else {
+      if (!single) {
         // Does the whole wavefront extend one row?  Then all lanes probe the
         // same lists, and short ones are staged once in LDS (wave_member).
         const int32_t i0 = __shfl(i, 0);
@@ -715,6 +700,70 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         }
       }
       keep |= (uint32_t)ok << it;
+    }
+
+    if (single) {
+      // Relations of the new position, one at a time for the whole tile.  With
+      // the candidate ids spanning at most 32*kTilePool values, the list window
+      // becomes an LDS bitmap over [cmin, cmax] (bit set: the arc exists and
+      // passes its predicate) and each candidate tests one bit; otherwise the
+      // staged windows (or the cut global lists) are binary-searched.
+      const int32_t cmin = s_misc[3];
+      const bool bitmap = tile_bitmap(cmin, s_misc[4]);
+      const int32_t words = (int32_t)(((int64_t)s_misc[4] - cmin) >> 5) + 1;
+      uint32_t* bm = reinterpret_cast<uint32_t*>(s_pool);
+      for (int32_t ci = 0; ci < ncons; ++ci) {
+        if (!__syncthreads_or(keep != 0)) break;  // also orders reuse of the bitmap
+        const int32_t desc = s_cons[ci];
+        const int q = desc & 31;
+        const bool in_dir = ((desc >> 5) & 1) != 0;
+        const bool req = ((desc >> 6) & 1) != 0;
+        const int32_t wlo = s_wlo[ci], whi = s_whi[ci];
+        const int32_t* lst = in_dir ? g.in_nbrs : g.out_nbrs;
+        const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
+        if (bitmap) {
+          for (int32_t x = threadIdx.x; x < words; x += kBlock) bm[x] = 0u;
+          __syncthreads();
+          for (int32_t x = wlo + threadIdx.x; x < whi; x += kBlock) {
+            const int32_t e = lst[x] - cmin;
+            bool pass = true;
+            if (need) pass = in_dir ? arc_ok(g, P, a, q, g.in_eid[x]) : arc_ok(g, P, q, a, x);
+            if (pass) atomicOr(&bm[e >> 5], 1u << (e & 31));
+          }
+          __syncthreads();
+#pragma unroll
+          for (int it = 0; it < kExpandItems; ++it) {
+            if ((keep >> it) & 1u) {
+              const int32_t o = cand[it] - cmin;
+              const bool hit = ((bm[o >> 5] >> (o & 31)) & 1u) != 0;
+              if (hit != req) keep &= ~(1u << it);
+            }
+          }
+        } else {
+          const int32_t woff = s_woff[ci];
+#pragma unroll
+          for (int it = 0; it < kExpandItems; ++it) {
+            if ((keep >> it) & 1u) {
+              int32_t pos;
+              if (woff >= 0) {
+                const int32_t x = lds_find(s_pool + woff, whi - wlo, cand[it]);
+                pos = x >= 0 ? wlo + x : -1;
+              } else {
+                pos = find_in(lst, wlo, whi, cand[it]);
+              }
+              bool ok;
+              if (!req)
+                ok = pos < 0;
+              else if (!need)
+                ok = pos >= 0;
+              else
+                ok = pos >= 0 && (in_dir ? arc_ok(g, P, a, q, g.in_eid[pos])
+                                         : arc_ok(g, P, q, a, pos));
+              if (!ok) keep &= ~(1u << it);
+            }
+          }
+        }
+      }
     }
 
     const unsigned long long cnt = __popc(keep);
