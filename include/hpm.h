@@ -125,6 +125,8 @@ typedef struct {
                                  result, used to check that reordering does not  \
                                  change it. */
 #define HPM_F_TIMING 0x2u     /* record per-phase device times (hpm_last_stats) */
+#define HPM_F_NO_FILTER 0x4u  /* do not pre-filter long shared candidate lists \
+                                 (same result; for checking and measurement) */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(hpm_match_opts)                         */
@@ -186,7 +188,8 @@ enum {
   HPM_K_EXPAND = 4,           /* extend partial mappings by one vertex               */
   HPM_K_LAST_LEVEL = 5,       /* final vertex: count (and write mappings)            */
   HPM_K_REDUCE = 6,           /* per-block counts -> total                           */
-  HPM_K_NUM = 7
+  HPM_K_FILTER = 7,           /* pre-filtering of long shared candidate lists        */
+  HPM_K_NUM = 8
 };
 
 /* Per-call statistics of the calling thread's most recent successful hpm_match.
@@ -204,6 +207,8 @@ typedef struct {
   uint64_t kernel_launches[HPM_K_NUM];
   double kernel_ms[HPM_K_NUM];
   double ms_total;               /* host wall time of the call                        */
+  uint64_t filtered_lists;       /* distinct candidate lists pre-filtered             */
+  uint64_t raw_work[HPM_MAX_K + 1]; /* candidates per depth before pre-filtering      */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

@@ -4,5 +4,6 @@ The matcher is libhpm.so (HIP kernels for gfx950 behind the C ABI of
 include/hpm.h); this package holds its sources (csrc/), the build script and a
 thin ctypes binding.
 """
-from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_REORDER, F_TIMING, Graph, HpmError,  # noqa: F401
+from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_FILTER, F_NO_REORDER, F_TIMING, Graph,  # noqa: F401
+                  HpmError,
                   abi_version, last_stats, load, match, plan_order, status_string)

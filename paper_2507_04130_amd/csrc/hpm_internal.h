@@ -22,6 +22,7 @@ constexpr int kLdsRowInts = 1024;     // partial-mapping entries staged in LDS p
 constexpr int kTilePool = 2048;       // LDS entries for staged adjacency lists per block
 constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront stages
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
+constexpr int kFilterMinLen = 256;    // pivot lists at least this long are pre-filtered
 
 // Per-vertex validator flags: bit p set when the vertex may be the image of
 // pattern position p (k <= 16 positions).
@@ -101,11 +102,33 @@ hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
 // Turns the lengths in off[0..r) into exclusive prefix sums; off[r] = total.
 hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream_t stream);
 // out_mode: 0 write depth d+1 rows; 1 count only; 2 count and write final rows.
+// fpool: pre-filtered candidate lists (rows whose pivot code has bit 1 set).
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
-                         const int32_t* rows, const int64_t* off, const int2* piv, int32_t r,
-                         int64_t w_begin, int64_t w_end, int out_mode, int32_t* out,
-                         unsigned long long* cursor, unsigned long long out_cap,
-                         unsigned long long* partials, int grid, hipStream_t stream);
+                         const int32_t* rows, const int64_t* off, const int2* piv,
+                         const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
+                         int out_mode, int32_t* out, unsigned long long* cursor,
+                         unsigned long long out_cap, unsigned long long* partials, int grid,
+                         hipStream_t stream);
+// Pivot-list filter.  off: the rows' exclusive length prefix sums.  keys[H]
+// must hold ~0 (empty) on entry, H a power of two above the number of rows
+// with a list of >= min_len entries.  Inserts their keys, then numbers the
+// distinct keys: counters[0] += slots, counters[1] += pool entries reserved;
+// slot_key / slot_region [H] describe each slot, dense[H] maps table slots.
+hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
+                              const int2* piv, const int64_t* off, int32_t min_len,
+                              unsigned long long* keys, uint32_t H, int32_t* dense,
+                              unsigned long long* slot_key, int64_t* slot_region,
+                              unsigned long long* counters, hipStream_t stream);
+hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
+                               int32_t a, int32_t nslots, const unsigned long long* slot_key,
+                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
+                               hipStream_t stream);
+// New list lengths into len[0..r) (+ block sums), long rows redirected in piv.
+hipError_t launch_filter_apply(const int32_t* rows, int32_t r, int32_t d, int2* piv,
+                               const int64_t* off, int64_t* len, int32_t min_len,
+                               const unsigned long long* keys, uint32_t H, const int32_t* dense,
+                               const int64_t* slot_region, const int32_t* fcount, int64_t* bsum,
+                               hipStream_t stream);
 // total[0] += sum(partials[0..nparts)); overflow[0] |= 1 on uint64 wrap.
 hipError_t launch_reduce_counts(const unsigned long long* partials, int32_t nparts,
                                 unsigned long long* total, uint32_t* overflow, hipStream_t stream);

@@ -377,7 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan*
   // For row i (a partial mapping of positions 0..d-1) pick, among the mapped
   // pattern neighbours b of position d, the adjacency list of f(b) in the
   // arc's direction with the fewest entries: every image of position d lies in
-  // it.  piv[i] = {(b << 1) | via_out, first index of that list}.
+  // it.  piv[i] = {(b << 2) | via_out, first index of that list}; bit 1 of the
+  // code is set later when the row is redirected to a pre-filtered list.
   __shared__ int64_t s_scan[kWaves + 1];
   const uint32_t fw = P->fwd[d], bw = P->bwd[d];
   int64_t sum = 0;
@@ -392,12 +393,12 @@ __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan*
           if ((fw >> b) & 1u) {
             const int32_t lo = g.out_off[fb];
             const int32_t L = g.out_off[fb + 1] - lo;
-            if (L < best) { best = L; code = (b << 1) | 1; base = lo; }
+            if (L < best) { best = L; code = (b << 2) | 1; base = lo; }
           }
           if ((bw >> b) & 1u) {
             const int32_t lo = g.in_off[fb];
             const int32_t L = g.in_off[fb + 1] - lo;
-            if (L < best) { best = L; code = b << 1; base = lo; }
+            if (L < best) { best = L; code = b << 2; base = lo; }
           }
         }
       }
@@ -470,9 +471,9 @@ template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_expand(
     DevGraph g, const DevPlan* __restrict__ P, const vflag_t* __restrict__ vflag, int32_t d,
     const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
-    const int2* __restrict__ piv, int32_t r, int64_t w_begin, int64_t w_end,
-    int32_t* __restrict__ out, unsigned long long* __restrict__ cursor, unsigned long long out_cap,
-    unsigned long long* __restrict__ partials) {
+    const int2* __restrict__ piv, const int32_t* __restrict__ fpool, int32_t r, int64_t w_begin,
+    int64_t w_end, int32_t* __restrict__ out, unsigned long long* __restrict__ cursor,
+    unsigned long long out_cap, unsigned long long* __restrict__ partials) {
   // Work item w in [w_begin, w_end) is candidate j = w - off[i] of the row i
   // with off[i] <= w < off[i+1]: entry j of that row's pivot list.  A tile of
   // kExpandTile consecutive items covers rows [r_lo, r_hi]; their prefix sums,
@@ -526,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
     }
     if (single && threadIdx.x == 0) {
       const int2 pv = piv[r_lo];
-      const int32_t b = pv.x >> 1;
+      const int32_t b = pv.x >> 2;
       const bool vo = (pv.x & 1) != 0;
       int32_t n = 0;
       for (int q = 0; q < d; ++q) {
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       }
       s_misc[2] = n;
       const int64_t o = off[r_lo];
-      const int32_t* list = vo ? g.out_nbrs : g.in_nbrs;
+      const int32_t* list = (pv.x & 2) ? fpool : (vo ? g.out_nbrs : g.in_nbrs);
       s_misc[3] = list[pv.y + (int32_t)(tb - o)];
       s_misc[4] = list[pv.y + (int32_t)(te - 1 - o)];
     }
@@ -593,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       const int64_t w = tb + it * kBlock + threadIdx.x;
       const bool valid = w < te;
       int32_t i = r_lo, li = 0, c = 0, b = 0, pos = 0;
-      bool via_out = false;
+      bool via_out = false, filtered = false;
       if (valid) {
         int64_t oi;
         int2 pv;
@@ -623,10 +624,11 @@ __global__ __launch_bounds__(kBlock) void k_expand(
           oi = off[lo];
           pv = piv[lo];
         }
-        b = pv.x >> 1;
+        b = pv.x >> 2;
         via_out = (pv.x & 1) != 0;
+        filtered = (pv.x & 2) != 0;
         pos = pv.y + (int32_t)(w - oi);
-        c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
+        c = filtered ? fpool[pos] : (via_out ? g.out_nbrs[pos] : g.in_nbrs[pos]);
       }
       cand[it] = c;
       crow[it] = i;
@@ -636,10 +638,11 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       const int32_t* lrow = s_rows + li * d;
       auto rowv = [&](int q) -> int32_t { return rows_lds ? lrow[q] : grow[q]; };
 
-      // vertex validator for position a (predicates, degrees)
-      bool ok = valid && ((vflag[c] >> a) & 1u) != 0;
+      // vertex validator for position a (predicates, degrees); a pre-filtered
+      // list holds only candidates that passed it and the pivot-arc predicate
+      bool ok = valid && (filtered || ((vflag[c] >> a) & 1u) != 0);
       // predicate of the pivot arc itself
-      if (ok) {
+      if (ok && !filtered) {
         if (via_out) {
           if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
         } else if (P->amask[a][b]) {
@@ -803,6 +806,153 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   }
 }
 
+// ------------------------------------------------------------ pivot-list filter
+//
+// Rows of one depth often share a long pivot list (many partial mappings
+// extend the same hub).  Each distinct long list -- key (vertex, direction,
+// pivot position) -- is filtered once: the candidates that pass the vertex
+// validator of the new position and the predicate of the pivot arc, in list
+// order, go to a pool; the rows are then pointed at their filtered list.
+
+__device__ __forceinline__ uint64_t pivot_key(int32_t v, int32_t code) {
+  // vertex | direction bit | pivot position
+  return (uint64_t)(uint32_t)v | ((uint64_t)(code & 1) << 32) | ((uint64_t)(code >> 2) << 33);
+}
+
+__device__ __forceinline__ uint32_t key_hash(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  return (uint32_t)x;
+}
+
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Slot of key in the open-addressing table (keys[H], H a power of two).
+__device__ __forceinline__ uint32_t table_find(const unsigned long long* __restrict__ keys,
+                                               uint32_t H, unsigned long long key) {
+  uint32_t h = key_hash(key) & (H - 1);
+  while (keys[h] != key) h = (h + 1) & (H - 1);
+  return h;
+}
+
+// off: exclusive prefix sums of the rows' list lengths (off[r] = total).
+__global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restrict__ rows,
+                                                          int32_t r, int32_t d,
+                                                          const int2* __restrict__ piv,
+                                                          const int64_t* __restrict__ off,
+                                                          int32_t min_len,
+                                                          unsigned long long* __restrict__ keys,
+                                                          uint32_t H) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
+       i += (int64_t)gridDim.x * kBlock) {
+    if (off[i + 1] - off[i] < min_len) continue;
+    const int32_t code = piv[i].x;
+    const unsigned long long key = pivot_key(rows[i * d + (code >> 2)], code);
+    uint32_t h = key_hash(key) & (H - 1);
+    while (true) {  // H exceeds the number of rows, so a free slot exists
+      const unsigned long long prev = atomicCAS(&keys[h], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) break;
+      h = (h + 1) & (H - 1);
+    }
+  }
+}
+
+// Dense ids and pool regions for the occupied slots.  counters[0] = slots,
+// counters[1] = pool entries reserved (sum of raw list lengths).
+__global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
+                                                          const unsigned long long* __restrict__ keys,
+                                                          uint32_t H, int32_t* __restrict__ dense,
+                                                          unsigned long long* __restrict__ slot_key,
+                                                          int64_t* __restrict__ slot_region,
+                                                          unsigned long long* __restrict__ counters) {
+  for (int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x; h < H;
+       h += (int64_t)gridDim.x * kBlock) {
+    const unsigned long long key = keys[h];
+    if (key == kEmptyKey) continue;
+    const int32_t v = (int32_t)(key & 0xffffffffull);
+    const bool out_dir = ((key >> 32) & 1ull) != 0;
+    const int32_t L = out_dir ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
+    const unsigned long long s = atomicAdd(&counters[0], 1ull);
+    dense[h] = (int32_t)s;
+    slot_key[s] = key;
+    slot_region[s] = (int64_t)atomicAdd(&counters[1], (unsigned long long)L);
+  }
+}
+
+// One block per distinct list: order-preserving compaction of the candidates
+// that pass the vertex validator of position a and the pivot-arc predicate.
+__global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
+                                                         const vflag_t* __restrict__ vflag,
+                                                         int32_t a,
+                                                         const unsigned long long* __restrict__ slot_key,
+                                                         const int64_t* __restrict__ slot_region,
+                                                         int32_t* __restrict__ pool,
+                                                         int32_t* __restrict__ fcount) {
+  __shared__ int32_t s_scan[kWaves + 1];
+  const unsigned long long key = slot_key[blockIdx.x];
+  const int32_t v = (int32_t)(key & 0xffffffffull);
+  const bool out_dir = ((key >> 32) & 1ull) != 0;
+  const int32_t b = (int32_t)(key >> 33);
+  const int32_t lo = out_dir ? g.out_off[v] : g.in_off[v];
+  const int32_t hi = out_dir ? g.out_off[v + 1] : g.in_off[v + 1];
+  const int32_t* lst = out_dir ? g.out_nbrs : g.in_nbrs;
+  int32_t* dst = pool + slot_region[blockIdx.x];
+  int32_t run = 0;
+  for (int32_t base = lo; base < hi; base += kBlock) {
+    const int32_t x = base + threadIdx.x;
+    int32_t c = 0;
+    bool ok = false;
+    if (x < hi) {
+      c = lst[x];
+      ok = ((vflag[c] >> a) & 1u) != 0;
+      if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok(g, P, a, b, g.in_eid[x]);
+    }
+    int32_t tot;
+    const int32_t ex = block_exclusive_scan<int32_t>(ok ? 1 : 0, s_scan, &tot);
+    if (ok) dst[run + ex] = c;
+    run += tot;
+  }
+  if (threadIdx.x == 0) fcount[blockIdx.x] = run;
+}
+
+// Redirect long rows to their filtered list: new lengths go to len[0..r) and
+// their per-block sums to bsum (same tiling as k_row_pivot), ready for
+// launch_scan_lengths.  off holds the old prefix sums.
+__global__ __launch_bounds__(kBlock) void k_filter_apply(const int32_t* __restrict__ rows,
+                                                         int32_t r, int32_t d,
+                                                         int2* __restrict__ piv,
+                                                         const int64_t* __restrict__ off,
+                                                         int64_t* __restrict__ len,
+                                                         int32_t min_len,
+                                                         const unsigned long long* __restrict__ keys,
+                                                         uint32_t H,
+                                                         const int32_t* __restrict__ dense,
+                                                         const int64_t* __restrict__ slot_region,
+                                                         const int32_t* __restrict__ fcount,
+                                                         int64_t* __restrict__ bsum) {
+  __shared__ int64_t s_scan[kWaves + 1];
+  int64_t sum = 0;
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+    if (i < r) {
+      int64_t L = off[i + 1] - off[i];
+      if (L >= min_len) {
+        const int2 pv = piv[i];
+        const unsigned long long key = pivot_key(rows[i * d + (pv.x >> 2)], pv.x);
+        const int32_t sidx = dense[table_find(keys, H, key)];
+        piv[i] = make_int2(pv.x | 2, (int32_t)slot_region[sidx]);
+        L = fcount[sidx];
+      }
+      len[i] = L;
+      sum += L;
+    }
+  }
+  const int64_t tot = block_sum<int64_t>(sum, s_scan);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_counts(const unsigned long long* __restrict__ partials,
                                                           int32_t nparts,
                                                           unsigned long long* __restrict__ total,
@@ -921,25 +1071,63 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 }
 
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
-                         const int32_t* rows, const int64_t* off, const int2* piv, int32_t r,
-                         int64_t w_begin, int64_t w_end, int out_mode, int32_t* out,
-                         unsigned long long* cursor, unsigned long long out_cap,
-                         unsigned long long* partials, int grid, hipStream_t stream) {
+                         const int32_t* rows, const int64_t* off, const int2* piv,
+                         const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
+                         int out_mode, int32_t* out, unsigned long long* cursor,
+                         unsigned long long out_cap, unsigned long long* partials, int grid,
+                         hipStream_t stream) {
   if (w_end <= w_begin || r <= 0) return hipSuccess;
   switch (out_mode) {
     case 0:
-      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
-                                               w_end, out, cursor, out_cap, partials);
+      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+                                               w_begin, w_end, out, cursor, out_cap, partials);
       break;
     case 1:
-      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
-                                               w_end, out, cursor, out_cap, partials);
+      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+                                               w_begin, w_end, out, cursor, out_cap, partials);
       break;
     default:
-      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, r, w_begin,
-                                               w_end, out, cursor, out_cap, partials);
+      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+                                               w_begin, w_end, out, cursor, out_cap, partials);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
+                              const int2* piv, const int64_t* off, int32_t min_len,
+                              unsigned long long* keys, uint32_t H, int32_t* dense,
+                              unsigned long long* slot_key, int64_t* slot_region,
+                              unsigned long long* counters, hipStream_t stream) {
+  if (r <= 0) return hipSuccess;
+  k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(rows, r, d, piv, off,
+                                                                              min_len, keys, H);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_filter_assign<<<grid_for(H, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+      g, keys, H, dense, slot_key, slot_region, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
+                               int32_t a, int32_t nslots, const unsigned long long* slot_key,
+                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
+                               hipStream_t stream) {
+  if (nslots <= 0) return hipSuccess;
+  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, vflag, a, slot_key, slot_region, pool,
+                                                fcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_apply(const int32_t* rows, int32_t r, int32_t d, int2* piv,
+                               const int64_t* off, int64_t* len, int32_t min_len,
+                               const unsigned long long* keys, uint32_t H, const int32_t* dense,
+                               const int64_t* slot_region, const int32_t* fcount, int64_t* bsum,
+                               hipStream_t stream) {
+  if (r <= 0) return hipSuccess;
+  const int nb = (int)(((int64_t)r + kPivotTile - 1) / kPivotTile);
+  k_filter_apply<<<nb, kBlock, 0, stream>>>(rows, r, d, piv, off, len, min_len, keys, H, dense,
+                                            slot_region, fcount, bsum);
   return hipGetLastError();
 }
 

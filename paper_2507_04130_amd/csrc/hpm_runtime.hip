@@ -97,6 +97,10 @@ struct DevBuf {
 struct Workspace {
   DevBuf plan, vflag, counters, partials, rows2;
   DevBuf off[kMaxK], piv[kMaxK], bsum[kMaxK], rows[kMaxK];
+  // pivot-list filter: per depth the filtered lists and the rows' new prefix
+  // sums; shared by all depths the hash table and slot descriptors
+  DevBuf fpool[kMaxK], off2[kMaxK];
+  DevBuf fkeys, fdense, fslot_key, fslot_region, fcount;
   unsigned long long* host = nullptr;  // pinned readback slots
   DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
   std::vector<hipEvent_t> events;
@@ -106,13 +110,21 @@ struct Workspace {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
   size_t held() const {
-    size_t s = plan.bytes + vflag.bytes + counters.bytes + partials.bytes + rows2.bytes;
-    for (int d = 0; d < kMaxK; ++d) s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes;
+    size_t s = plan.bytes + vflag.bytes + counters.bytes + partials.bytes + rows2.bytes +
+               fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
+    for (int d = 0; d < kMaxK; ++d)
+      s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
+           off2[d].bytes;
     return s;
   }
   void release_all() {
     plan.release(); vflag.release(); counters.release(); partials.release(); rows2.release();
-    for (int d = 0; d < kMaxK; ++d) { off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release(); }
+    fkeys.release(); fdense.release(); fslot_key.release(); fslot_region.release();
+    fcount.release();
+    for (int d = 0; d < kMaxK; ++d) {
+      off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
+      fpool[d].release(); off2[d].release();
+    }
   }
 };
 
@@ -367,7 +379,13 @@ DevPlan build_dev_plan(const hpm_pattern* p, const PatternInfo& P, const std::ve
 
 // ------------------------------------------------------------ matcher
 
-enum : int { kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3, kCntSlots = 4 };
+enum : int {
+  kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3, kCntSlots = 4,
+  kCntFilterSlots = 5, kCntFilterPool = 6
+};
+
+// Pre-filter pivot lists only when a depth has at least this many candidates.
+constexpr int64_t kFilterMinWork = int64_t(1) << 22;
 
 struct Matcher {
   hpm_graph* G;
@@ -379,9 +397,11 @@ struct Matcher {
   int32_t* maps;
   uint64_t cap;
   bool timing;
+  bool filter;
   int max_grid;
   int64_t cap2 = 0;     // depth-2 rows per arc chunk
   int64_t chunk = 0;    // rows per frontier chunk at depth >= 3
+  uint64_t budget = 0;  // scratch limit of the call
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -460,6 +480,66 @@ struct Matcher {
     W->bsum[d].ensure((size_t)(nb + 1) * sizeof(int64_t), stream);
   }
 
+  // Point rows whose pivot list has >= kFilterMinLen entries at a filtered copy
+  // of that list (one per distinct list).  On success *offp / *fpool / *work
+  // describe the new candidate ranges; otherwise nothing changes.
+  void filter_pivots(int32_t d, const int32_t* rows, int64_t r, int2* piv, const int64_t* off,
+                     const int64_t** offp, const int32_t** fpool, int64_t* work) {
+    const int64_t max_long = std::min<int64_t>(r, *work / hpm::kFilterMinLen);
+    if (max_long == 0) return;
+    uint32_t H = 1024;
+    while ((int64_t)H < 2 * max_long) H <<= 1;
+    const uint64_t table_bytes = (uint64_t)H * (8 + 4 + 8 + 8);
+    if (W->held() + table_bytes > budget) return;
+    W->fkeys.ensure((size_t)H * 8, stream);
+    W->fdense.ensure((size_t)H * 4, stream);
+    W->fslot_key.ensure((size_t)H * 8, stream);
+    W->fslot_region.ensure((size_t)H * 8, stream);
+    auto* keys = W->fkeys.as<unsigned long long>();
+    hip_check(hipMemsetAsync(keys, 0xff, (size_t)H * 8, stream), "memset");
+    hip_check(hipMemsetAsync(counters() + kCntFilterSlots, 0, 2 * sizeof(unsigned long long),
+                             stream),
+              "memset");
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_filter_keys(g, rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, keys,
+                                     H, W->fdense.as<int32_t>(),
+                                     W->fslot_key.as<unsigned long long>(),
+                                     W->fslot_region.as<int64_t>(), counters() + kCntFilterSlots,
+                                     stream);
+    });
+    hip_check(hipMemcpyAsync(W->host + kCntFilterSlots, counters() + kCntFilterSlots,
+                             2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+              "readback");
+    sync();
+    const int64_t nslots = (int64_t)W->host[kCntFilterSlots];
+    const int64_t pool = (int64_t)W->host[kCntFilterPool];
+    if (nslots == 0 || pool >= INT32_MAX) return;
+    const uint64_t more = (uint64_t)pool * 4 + (uint64_t)nslots * 4 + (uint64_t)(r + 1) * 8;
+    if (W->held() + more > budget) return;
+    W->fpool[d].ensure((size_t)std::max<int64_t>(pool, 1) * 4, stream);
+    W->fcount.ensure((size_t)nslots * 4, stream);
+    W->off2[d].ensure((size_t)(r + 1) * 8, stream);
+    int64_t* off2 = W->off2[d].as<int64_t>();
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_filter_lists(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, (int32_t)nslots,
+                                      W->fslot_key.as<unsigned long long>(),
+                                      W->fslot_region.as<int64_t>(), W->fpool[d].as<int32_t>(),
+                                      W->fcount.as<int32_t>(), stream);
+    });
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_filter_apply(rows, (int32_t)r, d, piv, off, off2, hpm::kFilterMinLen,
+                                      keys, H, W->fdense.as<int32_t>(),
+                                      W->fslot_region.as<int64_t>(), W->fcount.as<int32_t>(),
+                                      W->bsum[d].as<int64_t>(), stream);
+    });
+    launch(HPM_K_PREFIX_SUM,
+           [&] { return hpm::launch_scan_lengths(off2, (int32_t)r, W->bsum[d].as<int64_t>(), stream); });
+    *work = read_i64(off2 + r);
+    *offp = off2;
+    *fpool = W->fpool[d].as<int32_t>();
+    st.filtered_lists += (uint64_t)nslots;
+  }
+
   // Extend the r rows (each d entries) in `rows` to full embeddings.
   void process_depth(int32_t d, const int32_t* rows, int64_t r) {
     if (r == 0) return;
@@ -471,17 +551,21 @@ struct Matcher {
       return hpm::launch_row_pivot(g, dplan(), d, rows, (int32_t)r, piv, off, bsum, stream);
     });
     launch(HPM_K_PREFIX_SUM, [&] { return hpm::launch_scan_lengths(off, (int32_t)r, bsum, stream); });
-    const int64_t work = read_i64(off + r);
+    int64_t work = read_i64(off + r);
+    st.raw_work[d] += (uint64_t)work;
+    const int64_t* offp = off;
+    const int32_t* fpool = nullptr;
+    if (filter && work >= kFilterMinWork) filter_pivots(d, rows, r, piv, off, &offp, &fpool, &work);
     st.work[d] += (uint64_t)work;
     if (work == 0) return;
     if (d == k - 1) {
       const int grid = grid_for(work, hpm::kExpandTile);
       const int mode = maps ? 2 : 1;
       launch(HPM_K_LAST_LEVEL, [&] {
-        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, off, piv,
-                                  (int32_t)r, 0, work, mode, maps,
-                                  counters() + kCntEmit, maps ? cap : 0,
-                                  W->partials.as<unsigned long long>(), grid, stream);
+        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, offp, piv,
+                                  fpool, (int32_t)r, 0, work, mode, maps, counters() + kCntEmit,
+                                  maps ? cap : 0, W->partials.as<unsigned long long>(), grid,
+                                  stream);
       });
       launch(HPM_K_REDUCE, [&] {
         return hpm::launch_reduce_counts(W->partials.as<unsigned long long>(), grid,
@@ -501,9 +585,9 @@ struct Matcher {
       zero_counter(kCntCursor);
       const int grid = grid_for(n_items, hpm::kExpandTile);
       launch(HPM_K_EXPAND, [&] {
-        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, off, piv,
-                                  (int32_t)r, w0, w1, 0, out,
-                                  counters() + kCntCursor, (unsigned long long)n_items,
+        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, offp, piv,
+                                  fpool, (int32_t)r, w0, w1, 0, out, counters() + kCntCursor,
+                                  (unsigned long long)n_items,
                                   W->partials.as<unsigned long long>(), grid, stream);
       });
       const int64_t r1 = (int64_t)read_counter(kCntCursor);
@@ -788,9 +872,10 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
       hip_check(hipHostMalloc((void**)&W->host_plan, sizeof(DevPlan)), "hipHostMalloc");
 
     Matcher M{G, W, stream, G->view(), plan, k, mappings, mappings ? cap : 0,
-              (flags & HPM_F_TIMING) != 0, max_grid};
+              (flags & HPM_F_TIMING) != 0, (flags & HPM_F_NO_FILTER) == 0, max_grid};
     M.cap2 = cap2;
     M.chunk = chunk;
+    M.budget = budget;
     W->plan.ensure(sizeof(DevPlan), stream);
     W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1) * sizeof(hpm::vflag_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);

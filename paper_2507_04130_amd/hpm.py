@@ -20,9 +20,10 @@ ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
 F_TIMING = 0x2
+F_NO_FILTER = 0x4
 MAX_K = 16
 KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand", "last_level",
-           "reduce")
+           "reduce", "filter")
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
@@ -54,7 +55,8 @@ class _Stats(ctypes.Structure):
                 ("rows", ctypes.c_uint64 * (MAX_K + 1)), ("work", ctypes.c_uint64 * (MAX_K + 1)),
                 ("chunks", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
                 ("kernel_launches", ctypes.c_uint64 * len(KERNELS)),
-                ("kernel_ms", ctypes.c_double * len(KERNELS)), ("ms_total", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double * len(KERNELS)), ("ms_total", ctypes.c_double),
+                ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1))]
 
 
 _lib = None
@@ -233,6 +235,7 @@ def last_stats() -> dict:
         "scratch_bytes": s.scratch_bytes,
         "kernel_launches": dict(zip(KERNELS, list(s.kernel_launches))),
         "kernel_ms": dict(zip(KERNELS, list(s.kernel_ms))), "ms_total": s.ms_total,
+        "filtered_lists": s.filtered_lists, "raw_work": list(s.raw_work),
     }
 
 

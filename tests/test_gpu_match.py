@@ -297,3 +297,24 @@ def test_repeated_calls_are_deterministic():
         again = gpu_rows(dg, p, mode)
         assert again[0] == first[0]
         np.testing.assert_array_equal(again[1], first[1])
+
+
+def test_prefiltered_lists_change_nothing():
+    # Large-work depths pre-filter long shared candidate lists; the result must
+    # equal the unfiltered path and the oracle.
+    g = rmat(10, 1 << 13, seed=31)
+    dg = hpm.Graph.from_host(g)
+    used = 0
+    for name, mode in (("star3_back", ISO), ("cycle4", MONO), ("ffl_tail", MONO)):
+        p = motif(name)
+        c0, r0 = gpu_rows(dg, p, mode, flags=hpm.F_NO_FILTER)
+        assert hpm.last_stats()["filtered_lists"] == 0
+        c1, r1 = gpu_rows(dg, p, mode)
+        used += hpm.last_stats()["filtered_lists"]
+        assert c0 == c1
+        np.testing.assert_array_equal(r0, r1)
+        want = oracle.match(g, p, mode, threads=8, rows=False)
+        assert c1 == want.count
+        assert oracle.fingerprint(r1) == want.fingerprint
+        say(f"filter {name}/{mode}: count={c1} lists={hpm.last_stats()['filtered_lists']}")
+    assert used > 0
