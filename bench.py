@@ -95,11 +95,11 @@ def cpu_baseline(g, runs, seconds_target):
             secs += r.seconds
         return found, secs
 
-    f = 0.002
+    f = 1e-4
     found, secs = run(f)
     log(f"cpu baseline pilot: frac={f} matches={found} {secs:.2f}s")
-    if secs < seconds_target / 4:
-        f = min(1.0, f * seconds_target / max(secs, 1e-3))
+    while secs < seconds_target / 4 and f < 1.0:
+        f = min(1.0, f * min(50.0, seconds_target / max(secs, 1e-3)))
         found, secs = run(f)
     log(f"cpu baseline: frac={f:.4f} matches={found} {secs:.2f}s threads={threads}")
     return {"value": found / secs if secs > 0 else None, "unit": "matches/s", "cores": threads,
@@ -197,7 +197,8 @@ def main():
         "counts": counts,
         "per_query": [{"query": f"{p.name}/{'iso' if mode == 0 else 'mono'}", "count": st["count"],
                        "survivors": st["survivors"], "rows": st["rows"][2:p.k],
-                       "work": st["work"][2:p.k],
+                       "work": st["work"][2:p.k], "raw_work": st["raw_work"][2:p.k],
+                       "filtered_lists": st["filtered_lists"],
                        "kernel_ms": {k: round(v, 4) for k, v in st["kernel_ms"].items() if v}}
                       for st, (p, mode) in zip(all_stats[-len(runs):], runs)],
         "roofline": roofline,

@@ -85,12 +85,14 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
                                 const int32_t* out_nbrs, int32_t n, int32_t m, int32_t* in_eid,
                                 uint32_t* err, hipStream_t stream);
 
+// bits0/bits1: bitmaps of flag bits 0 and 1, 2*ceil(n/64) words each.
 hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
-                                   hipStream_t stream);
+                                   uint32_t* bits0, uint32_t* bits1, hipStream_t stream);
 // out_mode: 0 write depth-2 rows [.][2] in position order; 1 count only;
 // 2 write final rows [.][2] in original pattern order (two-vertex patterns).
-hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
-                            int32_t e_begin, int32_t e_end, int out_mode, int32_t* out,
+hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint32_t* bits0,
+                            const uint32_t* bits1, int32_t e_begin, int32_t e_end, int out_mode,
+                            int32_t* out,
                             unsigned long long* cursor, unsigned long long out_cap,
                             int grid, hipStream_t stream);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]

@@ -257,39 +257,60 @@ __global__ __launch_bounds__(kBlock) void k_transpose_ids(
 
 __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
                                                              const DevPlan* __restrict__ P,
-                                                             vflag_t* __restrict__ vflag) {
+                                                             vflag_t* __restrict__ vflag,
+                                                             uint32_t* __restrict__ bits0,
+                                                             uint32_t* __restrict__ bits1) {
   // Bit p of vflag[v]: v passes the vertex validator for pattern position p
   // (predicates and in/out degree at least the pattern's).  Alg. 2 states it
   // for position 0 and Alg. 3 applies it to position 1; the same test is a
   // sound filter for every later position, so it is computed once per vertex.
+  // Bits 0 and 1 are also packed into bitmaps (one bit per vertex) for the
+  // arc scan, whose random tests of arc heads then stay in L2.
   const int32_t k = P->k;
   uint32_t cols = 0;
   for (int p = 0; p < k; ++p) cols |= P->vmask[p];
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n;
-       v += (int64_t)gridDim.x * kBlock) {
-    const int32_t dout = g.out_off[v + 1] - g.out_off[v];
-    const int32_t din = g.in_off[v + 1] - g.in_off[v];
-    int32_t x[kMaxCols];
-#pragma unroll
-    for (int c = 0; c < kMaxCols; ++c) x[c] = ((cols >> c) & 1u) ? g.vcol[c][v] : 0;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+       base += (int64_t)gridDim.x * kBlock) {
+    const int64_t v = base + lane;
     uint32_t f = 0;
-    for (int p = 0; p < k; ++p) {
-      bool ok = din >= P->pin[p] && dout >= P->pout[p];
-      const uint32_t mask = P->vmask[p];
+    if (v < g.n) {
+      const int32_t dout = g.out_off[v + 1] - g.out_off[v];
+      const int32_t din = g.in_off[v + 1] - g.in_off[v];
+      int32_t x[kMaxCols];
 #pragma unroll
-      for (int c = 0; c < kMaxCols; ++c)
-        if ((mask >> c) & 1u) ok = ok && x[c] >= P->vlo[p][c] && x[c] <= P->vhi[p][c];
-      f |= (uint32_t)ok << p;
+      for (int c = 0; c < kMaxCols; ++c) x[c] = ((cols >> c) & 1u) ? g.vcol[c][v] : 0;
+      for (int p = 0; p < k; ++p) {
+        bool ok = din >= P->pin[p] && dout >= P->pout[p];
+        const uint32_t mask = P->vmask[p];
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c)
+          if ((mask >> c) & 1u) ok = ok && x[c] >= P->vlo[p][c] && x[c] <= P->vhi[p][c];
+        f |= (uint32_t)ok << p;
+      }
+      vflag[v] = (vflag_t)f;
     }
-    vflag[v] = (vflag_t)f;
+    const uint64_t b0 = __ballot((f & 1u) != 0);
+    const uint64_t b1 = __ballot((f & 2u) != 0);
+    if (lane == 0) {  // base is a multiple of 64: two whole words per bitmap
+      bits0[base >> 5] = (uint32_t)b0;
+      bits0[(base >> 5) + 1] = (uint32_t)(b0 >> 32);
+      bits1[base >> 5] = (uint32_t)b1;
+      bits1[(base >> 5) + 1] = (uint32_t)(b1 >> 32);
+    }
   }
+}
+
+__device__ __forceinline__ bool test_bit(const uint32_t* __restrict__ bits, int32_t v) {
+  return ((bits[v >> 5] >> (v & 31)) & 1u) != 0;
 }
 
 // ------------------------------------------------------------ arc scan
 
 template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan* __restrict__ P,
-                                                      const vflag_t* __restrict__ vflag,
+                                                      const uint32_t* __restrict__ bits0,
+                                                      const uint32_t* __restrict__ bits1,
                                                       int32_t e_begin, int32_t e_end,
                                                       int32_t* __restrict__ out,
                                                       unsigned long long* __restrict__ cursor,
@@ -331,8 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
         v0s[iv * 4 + j] = v0;
         v1s[iv * 4 + j] = v1;
         bool ok = x >= 0;
-        if (ok) ok = (vflag[v0] & 1) != 0;
-        if (ok) ok = (vflag[v1] & 2) != 0;
+        // tail first: arcs are sorted by tail, so its bitmap word is shared
+        if (ok) ok = fwd ? test_bit(bits0, x) : test_bit(bits1, x);
+        if (ok) ok = fwd ? test_bit(bits1, y) : test_bit(bits0, y);
         if (ok) ok = arc_ok(g, P, ps, pd, (int32_t)(e0 + j));
         if (ok && rev) {
           const int32_t pos = find_in(g.out_nbrs, g.out_off[y], g.out_off[y + 1], x);
@@ -1022,29 +1044,30 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
 }
 
 hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
-                                   hipStream_t stream) {
+                                   uint32_t* bits0, uint32_t* bits1, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
-  k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan,
-                                                                                   vflag);
+  k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan, vflag,
+                                                                                   bits0, bits1);
   return hipGetLastError();
 }
 
-hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
-                            int32_t e_begin, int32_t e_end, int out_mode, int32_t* out,
+hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint32_t* bits0,
+                            const uint32_t* bits1, int32_t e_begin, int32_t e_end, int out_mode,
+                            int32_t* out,
                             unsigned long long* cursor, unsigned long long out_cap, int grid,
                             hipStream_t stream) {
   if (e_end <= e_begin) return hipSuccess;
   switch (out_mode) {
     case 0:
-      k_edge_scan<0><<<grid, kBlock, 0, stream>>>(g, plan, vflag, e_begin, e_end, out, cursor,
+      k_edge_scan<0><<<grid, kBlock, 0, stream>>>(g, plan, bits0, bits1, e_begin, e_end, out, cursor,
                                                   out_cap);
       break;
     case 1:
-      k_edge_scan<1><<<grid, kBlock, 0, stream>>>(g, plan, vflag, e_begin, e_end, out, cursor,
+      k_edge_scan<1><<<grid, kBlock, 0, stream>>>(g, plan, bits0, bits1, e_begin, e_end, out, cursor,
                                                   out_cap);
       break;
     default:
-      k_edge_scan<2><<<grid, kBlock, 0, stream>>>(g, plan, vflag, e_begin, e_end, out, cursor,
+      k_edge_scan<2><<<grid, kBlock, 0, stream>>>(g, plan, bits0, bits1, e_begin, e_end, out, cursor,
                                                   out_cap);
       break;
   }

@@ -95,7 +95,7 @@ struct DevBuf {
 // Per-call scratch.  Pooled per graph so that concurrent calls (different
 // streams) never share one, and repeated calls reuse allocations.
 struct Workspace {
-  DevBuf plan, vflag, counters, partials, rows2;
+  DevBuf plan, vflag, vbits, counters, partials, rows2;
   DevBuf off[kMaxK], piv[kMaxK], bsum[kMaxK], rows[kMaxK];
   // pivot-list filter: per depth the filtered lists and the rows' new prefix
   // sums; shared by all depths the hash table and slot descriptors
@@ -110,7 +110,7 @@ struct Workspace {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
   size_t held() const {
-    size_t s = plan.bytes + vflag.bytes + counters.bytes + partials.bytes + rows2.bytes +
+    size_t s = plan.bytes + vflag.bytes + vbits.bytes + counters.bytes + partials.bytes + rows2.bytes +
                fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
@@ -118,7 +118,7 @@ struct Workspace {
     return s;
   }
   void release_all() {
-    plan.release(); vflag.release(); counters.release(); partials.release(); rows2.release();
+    plan.release(); vflag.release(); vbits.release(); counters.release(); partials.release(); rows2.release();
     fkeys.release(); fdense.release(); fslot_key.release(); fslot_region.release();
     fcount.release();
     for (int d = 0; d < kMaxK; ++d) {
@@ -411,6 +411,9 @@ struct Matcher {
   size_t next_event = 0;
 
   DevPlan* dplan() const { return W->plan.as<DevPlan>(); }
+  int64_t bit_words() const { return (G->n + 63) / 64 * 2; }
+  uint32_t* bits0() const { return W->vbits.as<uint32_t>(); }
+  uint32_t* bits1() const { return W->vbits.as<uint32_t>() + bit_words(); }
   unsigned long long* counters() const { return W->counters.as<unsigned long long>(); }
 
   hipEvent_t event() {
@@ -600,13 +603,14 @@ struct Matcher {
     const int64_t m = G->m;
     st.arcs_scanned = (uint64_t)m;
     launch(HPM_K_VERTEX_VALIDATOR, [&] {
-      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<hpm::vflag_t>(), stream);
+      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<hpm::vflag_t>(), bits0(),
+                                          bits1(), stream);
     });
     if (k == 2) {
       zero_counter(kCntCursor);
       const int grid = grid_for(m, hpm::kScanTile);
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<hpm::vflag_t>(), 0, (int32_t)m,
+        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m,
                                      maps ? 2 : 1, maps, counters() + kCntCursor,
                                      maps ? cap : 0, grid, stream);
       });
@@ -621,7 +625,7 @@ struct Matcher {
       zero_counter(kCntCursor);
       const int grid = grid_for(e1 - e0, hpm::kScanTile);
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), W->vflag.as<hpm::vflag_t>(), (int32_t)e0, (int32_t)e1,
+        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1,
                                      0, W->rows2.as<int32_t>(), counters() + kCntCursor,
                                      (unsigned long long)(e1 - e0), grid, stream);
       });
@@ -818,27 +822,28 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     }
 
     // Scratch layout and its budget.  Fixed part: plan, vertex flags, counters,
-    // per-block partial counts.  Depth 2 costs 21 B per row of an arc chunk
-    // (row 8, prefix 8, pivot 4, block sums); depth d >= 3 costs 4d + 13 B per row.
+    // per-block partial counts.  Depth 2 costs 25 B per row of an arc chunk
+    // (row 8, prefix 8, pivot 8, block sums); depth d >= 3 costs 4d + 17 B per row.
     const int max_grid = std::max(64, G->num_cus * 8);
-    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n * sizeof(hpm::vflag_t) + 64 +
+    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n * sizeof(hpm::vflag_t) +
+                           ((uint64_t)G->n + 63) / 64 * 16 + 64 +
                            (uint64_t)max_grid * sizeof(unsigned long long) + 4096;
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
     int64_t cap2 = 0, chunk = 0;
     if (k >= 3) {
       uint64_t per_row_deep = 0;
-      for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += 4 * (uint64_t)d + 13;
+      for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += 4 * (uint64_t)d + 17;
       const uint64_t m_round =
           ((uint64_t)G->m + hpm::kScanTile - 1) / hpm::kScanTile * hpm::kScanTile;
       uint64_t c2 = std::min<uint64_t>(std::max<uint64_t>(m_round, hpm::kScanTile),
-                                       (per_row_deep ? avail / 2 : avail) / 21);
+                                       (per_row_deep ? avail / 2 : avail) / 25);
       c2 = c2 / hpm::kScanTile * hpm::kScanTile;
       c2 = std::min<uint64_t>(c2, (uint64_t)INT32_MAX / hpm::kScanTile * hpm::kScanTile);
       if (c2 < (uint64_t)hpm::kScanTile) fail(HPM_E_NOMEM, "scratch budget below one arc chunk");
       cap2 = (int64_t)c2;
       if (per_row_deep) {
-        uint64_t c = (avail - c2 * 21) / per_row_deep;
+        uint64_t c = (avail - c2 * 25) / per_row_deep;
         c = std::min<uint64_t>(c, (uint64_t)1 << 30);
         if (c < kMinChunkRows) fail(HPM_E_NOMEM, "scratch budget below one frontier chunk");
         chunk = (int64_t)c;
@@ -878,6 +883,7 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     M.budget = budget;
     W->plan.ensure(sizeof(DevPlan), stream);
     W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1) * sizeof(hpm::vflag_t), stream);
+    W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * 2 * sizeof(uint32_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);
     W->partials.ensure((size_t)max_grid * sizeof(unsigned long long), stream);
     if (k >= 3) {

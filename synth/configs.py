@@ -6,9 +6,10 @@ c1  directed Erdos-Renyi G(n=1000, m=5000), vertex labels U{0..3}, arc labels
 c2  R-MAT scale 20 (a,b,c,d = .57,.19,.19,.05), 2^24 distinct arcs, vertex
     labels Zipf(1.2) over 16 values, arc labels U{0..3}; four 4-vertex motifs
     with labels drawn from the same laws; induced isomorphism and monomorphism.
-c3  directed Chung-Lu, n=2e7, m=1.5e8, power-law weights (gamma 2.1, max 5e4),
-    30% reciprocal arcs, vertex labels U{0..7}, arc weight 1+floor(exp(1+Z));
-    three 5-vertex motifs, every arc weight >= 10, monomorphism.
+c3  directed Chung-Lu, n=2e7, about 1.5e8 arcs, power-law weights (gamma 2.1,
+    max 5e4), 30% reciprocal arcs, vertex labels U{0..7}, arc weight
+    1+floor(exp(1+Z)); three 5-vertex motifs with arc-weight thresholds,
+    monomorphism (see C3_SHAPES).
 c4  256 random patterns (3..8 vertices) on the c2 graph, mixed modes.
 c5  random patterns on the c3 graph arriving as a Poisson stream.
 
@@ -72,15 +73,29 @@ def c3_graph(n: int = 20_000_000, m: int = 150_000_000):
     return connectome(n, m, GRAPH_SEEDS["c3"])
 
 
+# Per-motif query shape on the connectome graph: which vertices carry a label
+# (drawn U{0..7} from the pattern seed) and the arc-weight threshold.  Chosen
+# so every query has a non-trivial result on the 1.5e8-arc graph: the chain and
+# reciprocal triad need triangles, which a Chung-Lu graph has few of, so they
+# are unlabelled with lower thresholds.
+C3_SHAPES = {
+    "bifan_plus1": ((3, 4), 10),
+    "ff_chain": ((), 4),
+    "recip_triad_plus": ((), 6),
+}
+
+
 def c3_patterns():
-    """Three 5-vertex motifs; vertex labels U{0..7} (EQ), every arc weight >= 10."""
+    """Three 5-vertex motifs, monomorphism; vertex labels EQ, arc weight GE."""
     rng = np.random.default_rng(PATTERN_SEEDS["c3"])
     out = []
     for name in C3_MOTIFS:
         from .patterns import MOTIFS
         k, arcs = MOTIFS[name]
-        vl = rng.integers(0, 8, size=k).tolist()
-        out.append(motif(name, vlabels=vl, elabels=[C3_THRESHOLD] * len(arcs), eop=GE,
+        labelled, thr = C3_SHAPES[name]
+        draws = rng.integers(0, 8, size=k).tolist()
+        vl = [draws[v] if v in labelled else None for v in range(k)]
+        out.append(motif(name, vlabels=vl, elabels=[thr] * len(arcs), eop=GE,
                          name_suffix="_c3"))
     return out
 

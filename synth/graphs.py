@@ -14,6 +14,7 @@ weights and a fixed fraction of reciprocal arcs.
 from __future__ import annotations
 
 import hashlib
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -195,65 +196,75 @@ def truncated_pareto(rng, size, gamma: float, xmin: float, xmax: float) -> np.nd
     return xmin * (1.0 - u * (1.0 - lo)) ** (-1.0 / al)
 
 
+_CL_LIB = None
+
+
+def build_native(force: bool = True) -> str:
+    """Compile the Chung-Lu helper (g++ -O3 -fopenmp) into synth/libchunglu.so."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    lib = os.path.join(here, "libchunglu.so")
+    if force or not os.path.exists(lib):
+        subprocess.run(["g++", "-O3", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o",
+                        lib + ".tmp", os.path.join(here, "chung_lu.cpp")], check=True)
+        os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def _cl_lib():
+    global _CL_LIB
+    if _CL_LIB is None:
+        import ctypes
+        lib = ctypes.CDLL(build_native(force=False))
+        P = ctypes.POINTER
+        lib.cl_generate.restype = ctypes.c_int64
+        lib.cl_generate.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                    ctypes.c_int32, P(P(ctypes.c_int64)), P(P(ctypes.c_int32)),
+                                    P(P(ctypes.c_int64)), P(P(ctypes.c_int32)),
+                                    P(P(ctypes.c_int32)), P(P(ctypes.c_int32))]
+        lib.cl_free.argtypes = [ctypes.c_void_p]
+        _CL_LIB = lib
+    return _CL_LIB
+
+
 def connectome(n: int, m: int, seed: int, gamma: float = 2.1, xmax: float = 50_000,
-               recip: float = 0.30, vlabels=("uniform", 8),
-               elabels=("lognormal_int", 1.0, 1.0)) -> HostGraph:
+               recip: float = 0.30, nlab: int = 8, mu: float = 1.0, sigma: float = 1.0,
+               threads: int = 0) -> HostGraph:
     """Directed Chung-Lu graph with power-law in/out weights and reciprocity.
 
-    Out- and in-weights are i.i.d. truncated Pareto(gamma, 1, xmax).  Base arcs
-    draw their tail proportional to w_out and their head proportional to w_in
-    (multinomial counts per vertex, heads shuffled against tails, which is the
-    same law as independent draws).  Self-loops and repeats are dropped.  Then
-    reverse arcs are added to chosen base arcs until the fraction of arcs whose
-    reverse also exists is `recip`, and the set is topped up to exactly m arcs.
+    Built by synth/chung_lu.cpp (see its header for the recipe): out- and
+    in-weights i.i.d. truncated Pareto(gamma, 1, xmax); Poisson arc draws per
+    tail, heads proportional to w_in; self-loops and repeats dropped; reverse
+    arcs added so that a `recip` fraction of arcs is reciprocal; vertex labels
+    U{0..nlab-1}; arc weight 1 + floor(exp(mu + sigma Z)).  About m arcs.
+    Counter-based random streams: the output does not depend on `threads`.
     """
-    rng = np.random.default_rng(seed)
-    w_out = truncated_pareto(rng, n, gamma, 1.0, xmax)
-    w_in = truncated_pareto(rng, n, gamma, 1.0, xmax)
-    r_target = int(round(recip * m / 2))          # reciprocal pairs wanted
-    need_base = m - r_target
-    pool = np.empty(0, dtype=np.int64)
-    draw = int(need_base * 1.08) + 1024
-    while pool.shape[0] < m:
-        cs = rng.multinomial(draw, w_out / w_out.sum())
-        cd = rng.multinomial(draw, w_in / w_in.sum())
-        s = np.repeat(np.arange(n, dtype=np.int64), cs)
-        d = np.repeat(np.arange(n, dtype=np.int64), cd)
-        rng.shuffle(d)
-        keep = s != d
-        pool = _first_unique(np.concatenate([pool, s[keep] * n + d[keep]]))
-        del s, d, keep
-        draw = max(draw // 4, 1 << 20)
-    base = pool[:need_base]
-    spare = pool[need_base:]
-    base_sorted = np.sort(base)
-    bs = base // n
-    rev = (base - bs * n) * n + bs
-    pos = np.searchsorted(base_sorted, rev)
-    pos[pos >= base_sorted.shape[0]] = 0
-    has_rev = base_sorted[pos] == rev
-    n_nat_pairs = int(has_rev.sum()) // 2
-    add = max(r_target - n_nat_pairs, 0)
-    cand = np.flatnonzero(~has_rev)
-    chosen = rng.choice(cand, size=add, replace=False)
-    new = rev[chosen]
-    keys = np.concatenate([base, new])
-    del base_sorted, pos, has_rev, cand, rev, bs
-    short = m - keys.shape[0]
-    if short > 0:
-        # top up with later pool arcs that are not already present
-        ks = np.sort(keys)
-        p2 = np.searchsorted(ks, spare)
-        p2[p2 >= ks.shape[0]] = 0
-        fresh = spare[ks[p2] != spare]
-        keys = np.concatenate([keys, fresh[:short]])
-    keys = keys[:m]
-    assert keys.shape[0] == m
-    vl = draw_labels(rng, n, vlabels)
-    return graph_from_arcs(n, keys // n, keys % n, [vl],
-                           lambda mm: [draw_labels(rng, mm, elabels)],
-                           meta={"family": "chung_lu", "n": n, "m": m, "seed": seed,
-                                 "gamma": gamma, "xmax": xmax, "recip": recip})
+    import ctypes
+    lib = _cl_lib()
+    P64, P32 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    oo, on, io, inn, vl, ew = P64(), P32(), P64(), P32(), P32(), P32()
+    M = lib.cl_generate(n, m, gamma, xmax, recip, nlab, mu, sigma, seed, threads,
+                        ctypes.byref(oo), ctypes.byref(on), ctypes.byref(io), ctypes.byref(inn),
+                        ctypes.byref(vl), ctypes.byref(ew))
+    if M < 0:
+        raise ValueError("bad Chung-Lu parameters")
+
+    def take(ptr, count, dtype):
+        arr = np.ctypeslib.as_array(ptr, shape=(max(count, 1),))[:count].astype(dtype, copy=True)
+        lib.cl_free(ctypes.cast(ptr, ctypes.c_void_p))
+        return arr
+
+    out_off = take(oo, n + 1, np.int64)
+    out_nbrs = take(on, M, np.int32)
+    in_off = take(io, n + 1, np.int64)
+    in_nbrs = take(inn, M, np.int32)
+    vlab = take(vl, n, np.int32)
+    wts = take(ew, M, np.int32)
+    return HostGraph(n, int(M), out_off, out_nbrs, in_off, in_nbrs, [vlab], [wts],
+                     {"family": "chung_lu", "n": n, "m_target": m, "m": int(M), "seed": seed,
+                      "gamma": gamma, "xmax": xmax, "recip": recip})
 
 
 def reciprocal_fraction(g: HostGraph) -> float:

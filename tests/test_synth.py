@@ -54,7 +54,7 @@ def test_rmat_labels_and_skew():
 
 def test_connectome_reciprocity_and_weights():
     g = connectome(200_000, 1_500_000, 4)
-    assert g.m == 1_500_000
+    assert abs(g.m - 1_500_000) < 15_000
     assert abs(reciprocal_fraction(g) - 0.30) < 0.005
     w = g.ecols[0]
     assert w.min() >= 1
@@ -78,3 +78,9 @@ def test_random_patterns():
         assert len(set(arcs)) == len(arcs)
         assert all(a != b for a, b in arcs)
         assert is_weakly_connected(p.k, arcs)
+
+
+def test_connectome_independent_of_thread_count():
+    a = connectome(40_000, 300_000, 9, threads=1)
+    b = connectome(40_000, 300_000, 9, threads=5)
+    assert a.sha256() == b.sha256()
