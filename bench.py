@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--workload", default="rmat20", choices=["rmat20", "er1k", "chunglu"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the matcher shards by arc range across GPUs "
@@ -128,6 +131,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read and written")
+        del src, dst
     t0 = time.time()
     g, runs, desc = workload(args.workload)
     log(f"workload {args.workload}: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")

@@ -12,7 +12,7 @@ constexpr int kMaxK = 16;
 constexpr int kMaxCols = 4;
 constexpr int kBlock = 256;           // threads per block (4 wave64s)
 constexpr int kWaves = kBlock / 64;
-constexpr int kScanItems = 16;        // arcs per thread per tile in the arc scan
+constexpr int kScanItems = 8;         // arcs per thread per tile in the arc scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kExpandItems = 4;       // candidates per thread per tile in the extension
 constexpr int kExpandTile = kBlock * kExpandItems;
@@ -23,6 +23,7 @@ constexpr int kTilePool = 2048;       // LDS entries for staged adjacency lists 
 constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront stages
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
 constexpr int kFilterMinLen = 256;    // pivot lists at least this long are pre-filtered
+constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 
 // Per-vertex validator flags: bit p set when the vertex may be the image of
 // pattern position p (k <= 16 positions).
@@ -38,6 +39,7 @@ struct DevGraph {
   const int32_t* in_nbrs;   // [m]   tails, rows ascending
   const int32_t* src;       // [m]   tail of out-CSR arc e (edge-to-source index)
   const int32_t* in_eid;    // [m]   out-CSR arc id of in-CSR position j
+  const int32_t* rev_eid;   // [m]   out-CSR id of the reverse of arc e, or -1
   int32_t n_vcols, n_ecols;
   const int32_t* vcol[kMaxCols];  // [n] each
   const int32_t* ecol[kMaxCols];  // [m] each, out-CSR order
@@ -84,17 +86,34 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
                                 const int32_t* in_row, const int32_t* out_off,
                                 const int32_t* out_nbrs, int32_t n, int32_t m, int32_t* in_eid,
                                 uint32_t* err, hipStream_t stream);
+// rev_eid[e] = out-CSR id of arc (head -> tail) for out-CSR arc e, or -1.
+hipError_t launch_reverse_ids(const int32_t* out_off, const int32_t* out_nbrs, const int32_t* src,
+                              int32_t m, int32_t* rev_eid, hipStream_t stream);
 
 // bits0/bits1: bitmaps of flag bits 0 and 1, 2*ceil(n/64) words each.
 hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
                                    uint32_t* bits0, uint32_t* bits1, hipStream_t stream);
-// out_mode: 0 write depth-2 rows [.][2] in position order; 1 count only;
-// 2 write final rows [.][2] in original pattern order (two-vertex patterns).
+// out_mode 0: depth-2 rows [.][2] in position order, written into per-block
+//   regions of `out` (rows indexed like the chunk's arcs), per-block counts to
+//   blk_count[grid]; compact them with launch_rows2_compact + _gather.
+// out_mode 1: count only, per-block counts to blk_count[grid].
+// out_mode 2: final rows [.][2] in original pattern order (two-vertex
+//   patterns) into out[out_cap], slots reserved on *cursor.
 hipError_t launch_edge_scan(const DevGraph& g, const DevPlan* plan, const uint32_t* bits0,
                             const uint32_t* bits1, int32_t e_begin, int32_t e_end, int out_mode,
-                            int32_t* out,
-                            unsigned long long* cursor, unsigned long long out_cap,
-                            int grid, hipStream_t stream);
+                            int32_t* out, unsigned long long* cursor, unsigned long long out_cap,
+                            unsigned long long* blk_count, int grid, hipStream_t stream);
+// In place: blk_count[0..nb) -> exclusive prefix sums, blk_count[nb] = total.
+// blk_count must have nb + 1 entries; bsum ceil(nb / kPivotTile) + 1.
+hipError_t launch_rows2_compact(int64_t* blk_count, int32_t nb, int64_t* bsum,
+                                hipStream_t stream);
+// dense[0..s2) = the rows of the per-tile regions of a scan over [e_begin, e_end)
+// launched with nb = edge_scan_blocks(e_end - e_begin) blocks.
+hipError_t launch_rows2_gather(const int32_t* sparse, const int64_t* prefix, int32_t nb,
+                               int32_t e_begin, int32_t e_end, int32_t* dense, int64_t s2,
+                               hipStream_t stream);
+// Blocks for an arc scan over `arcs` arcs with out_mode 0 or 1 (one per tile).
+int64_t edge_scan_blocks(int64_t arcs);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]
 // ({code, list start}), len into off[0..r) and per-block sums into
 // bsum[ceil(r / kPivotTile)].

@@ -95,7 +95,7 @@ struct DevBuf {
 // Per-call scratch.  Pooled per graph so that concurrent calls (different
 // streams) never share one, and repeated calls reuse allocations.
 struct Workspace {
-  DevBuf plan, vflag, vbits, counters, partials, rows2;
+  DevBuf plan, vflag, vbits, counters, partials, blkcount, blkprefix, rows2, rows2d;
   DevBuf off[kMaxK], piv[kMaxK], bsum[kMaxK], rows[kMaxK];
   // pivot-list filter: per depth the filtered lists and the rows' new prefix
   // sums; shared by all depths the hash table and slot descriptors
@@ -110,7 +110,8 @@ struct Workspace {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
   size_t held() const {
-    size_t s = plan.bytes + vflag.bytes + vbits.bytes + counters.bytes + partials.bytes + rows2.bytes +
+    size_t s = plan.bytes + vflag.bytes + vbits.bytes + counters.bytes + partials.bytes +
+               blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
@@ -118,7 +119,8 @@ struct Workspace {
     return s;
   }
   void release_all() {
-    plan.release(); vflag.release(); vbits.release(); counters.release(); partials.release(); rows2.release();
+    plan.release(); vflag.release(); vbits.release(); counters.release(); partials.release();
+    blkcount.release(); blkprefix.release(); rows2.release(); rows2d.release();
     fkeys.release(); fdense.release(); fslot_key.release(); fslot_region.release();
     fcount.release();
     for (int d = 0; d < kMaxK; ++d) {
@@ -136,7 +138,7 @@ struct hpm_graph {
   int32_t n = 0;
   int64_t m = 0;
   int32_t n_vcols = 0, n_ecols = 0;
-  DevBuf out_off, out_nbrs, in_off, in_nbrs, src, in_eid;
+  DevBuf out_off, out_nbrs, in_off, in_nbrs, src, in_eid, rev_eid;
   DevBuf vcols[kMaxCols], ecols[kMaxCols];
   std::mutex mu;
   std::vector<Workspace*> pool;
@@ -146,7 +148,7 @@ struct hpm_graph {
   }
   uint64_t bytes() const {
     uint64_t s = out_off.bytes + out_nbrs.bytes + in_off.bytes + in_nbrs.bytes + src.bytes +
-                 in_eid.bytes;
+                 in_eid.bytes + rev_eid.bytes;
     for (int c = 0; c < kMaxCols; ++c) s += vcols[c].bytes + ecols[c].bytes;
     return s;
   }
@@ -160,6 +162,7 @@ struct hpm_graph {
     g.in_nbrs = in_nbrs.as<int32_t>();
     g.src = src.as<int32_t>();
     g.in_eid = in_eid.as<int32_t>();
+    g.rev_eid = rev_eid.as<int32_t>();
     g.n_vcols = n_vcols;
     g.n_ecols = n_ecols;
     for (int c = 0; c < kMaxCols; ++c) {
@@ -607,14 +610,33 @@ struct Matcher {
                                           bits1(), stream);
     });
     if (k == 2) {
-      zero_counter(kCntCursor);
       const int grid = grid_for(m, hpm::kScanTile);
-      launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m,
-                                     maps ? 2 : 1, maps, counters() + kCntCursor,
-                                     maps ? cap : 0, grid, stream);
-      });
-      const uint64_t c = read_counter(kCntCursor);
+      uint64_t c;
+      if (maps) {
+        zero_counter(kCntCursor);
+        launch(HPM_K_EDGE_SCAN, [&] {
+          return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 2, maps,
+                                       counters() + kCntCursor, cap,
+                                       W->partials.as<unsigned long long>(), grid, stream);
+        });
+        c = read_counter(kCntCursor);
+      } else {
+        const int nb = (int)hpm::edge_scan_blocks(m);
+        W->blkcount.ensure((size_t)nb * sizeof(unsigned long long), stream);
+        launch(HPM_K_EDGE_SCAN, [&] {
+          return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 1, nullptr,
+                                       nullptr, 0, W->blkcount.as<unsigned long long>(), nb,
+                                       stream);
+        });
+        launch(HPM_K_REDUCE, [&] {
+          return hpm::launch_reduce_counts(W->blkcount.as<unsigned long long>(), nb,
+                                           counters() + kCntTotal,
+                                           reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
+                                           stream);
+        });
+        c = read_counter(kCntTotal);
+        if (read_counter(kCntOverflow)) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
+      }
       st.survivors = c;
       st.rows[2] = c;
       st.count = c;
@@ -622,17 +644,30 @@ struct Matcher {
     }
     for (int64_t e0 = 0; e0 < m; e0 += cap2) {
       const int64_t e1 = std::min<int64_t>(m, e0 + cap2);
-      zero_counter(kCntCursor);
-      const int grid = grid_for(e1 - e0, hpm::kScanTile);
+      const int grid = (int)hpm::edge_scan_blocks(e1 - e0);
+      W->blkcount.ensure((size_t)(grid + 1) * sizeof(int64_t), stream);
+      W->blkprefix.ensure((size_t)(grid / hpm::kPivotTile + 2) * sizeof(int64_t), stream);
+      int64_t* cnt = W->blkcount.as<int64_t>();
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1,
-                                     0, W->rows2.as<int32_t>(), counters() + kCntCursor,
-                                     (unsigned long long)(e1 - e0), grid, stream);
+        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1, 0,
+                                     W->rows2.as<int32_t>(), nullptr,
+                                     (unsigned long long)(e1 - e0),
+                                     reinterpret_cast<unsigned long long*>(cnt), grid, stream);
       });
-      const int64_t s2 = (int64_t)read_counter(kCntCursor);
+      launch(HPM_K_PREFIX_SUM, [&] {
+        return hpm::launch_rows2_compact(cnt, grid, W->blkprefix.as<int64_t>(), stream);
+      });
+      const int64_t s2 = read_i64(cnt + grid);
       if (s2 > e1 - e0) fail(HPM_E_INTERNAL, "scan overflow");
       st.survivors += (uint64_t)s2;
-      process_depth(2, W->rows2.as<int32_t>(), s2);
+      if (s2 == 0) continue;
+      W->rows2d.ensure((size_t)s2 * 2 * sizeof(int32_t), stream);
+      ensure_depth(2, s2);
+      launch(HPM_K_PREFIX_SUM, [&] {
+        return hpm::launch_rows2_gather(W->rows2.as<int32_t>(), cnt, grid, (int32_t)e0,
+                                        (int32_t)e1, W->rows2d.as<int32_t>(), s2, stream);
+      });
+      process_depth(2, W->rows2d.as<int32_t>(), s2);
     }
     st.count = read_counter(kCntTotal);
     if (read_counter(kCntOverflow)) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
@@ -709,6 +744,7 @@ int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_o
     for (int c = 0; c < n_ecols; ++c) upload(G->ecols[c], ecols[c], mb, stream);
     G->src.ensure(mb ? mb : 4, stream);
     G->in_eid.ensure(mb ? mb : 4, stream);
+    G->rev_eid.ensure(mb ? mb : 4, stream);
     DevBuf in_row, err;
     in_row.ensure(mb ? mb : 4, stream);
     err.ensure(sizeof(uint32_t), stream);
@@ -734,6 +770,11 @@ int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_o
     hip_check(hipMemcpyAsync(&bits, e, sizeof(bits), hipMemcpyDeviceToHost, stream), "readback");
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (bits) fail(HPM_E_GRAPH, graph_error_text(bits));
+    // only on a valid graph: every head indexes out_off
+    hip_check(hpm::launch_reverse_ids(G->out_off.as<int32_t>(), G->out_nbrs.as<int32_t>(),
+                                      G->src.as<int32_t>(), mi, G->rev_eid.as<int32_t>(), stream),
+              "reverse ids");
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     *out = G.release();
     return HPM_OK;
   });
@@ -822,12 +863,13 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     }
 
     // Scratch layout and its budget.  Fixed part: plan, vertex flags, counters,
-    // per-block partial counts.  Depth 2 costs 25 B per row of an arc chunk
-    // (row 8, prefix 8, pivot 8, block sums); depth d >= 3 costs 4d + 17 B per row.
+    // per-block partial counts.  Depth 2 costs 33 B per arc of a chunk (scan
+    // region 8, dense row 8, prefix 8, pivot 8, per-tile counts and block
+    // sums); depth d >= 3 costs 4d + 17 B per row.
     const int max_grid = std::max(64, G->num_cus * 8);
     const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n * sizeof(hpm::vflag_t) +
                            ((uint64_t)G->n + 63) / 64 * 16 + 64 +
-                           (uint64_t)max_grid * sizeof(unsigned long long) + 4096;
+                           (uint64_t)max_grid * 2 * sizeof(unsigned long long) + 4096;
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
     int64_t cap2 = 0, chunk = 0;
@@ -837,13 +879,13 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
       const uint64_t m_round =
           ((uint64_t)G->m + hpm::kScanTile - 1) / hpm::kScanTile * hpm::kScanTile;
       uint64_t c2 = std::min<uint64_t>(std::max<uint64_t>(m_round, hpm::kScanTile),
-                                       (per_row_deep ? avail / 2 : avail) / 25);
+                                       (per_row_deep ? avail / 2 : avail) / 33);
       c2 = c2 / hpm::kScanTile * hpm::kScanTile;
       c2 = std::min<uint64_t>(c2, (uint64_t)INT32_MAX / hpm::kScanTile * hpm::kScanTile);
       if (c2 < (uint64_t)hpm::kScanTile) fail(HPM_E_NOMEM, "scratch budget below one arc chunk");
       cap2 = (int64_t)c2;
       if (per_row_deep) {
-        uint64_t c = (avail - c2 * 25) / per_row_deep;
+        uint64_t c = (avail - c2 * 33) / per_row_deep;
         c = std::min<uint64_t>(c, (uint64_t)1 << 30);
         if (c < kMinChunkRows) fail(HPM_E_NOMEM, "scratch budget below one frontier chunk");
         chunk = (int64_t)c;
@@ -889,7 +931,6 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     if (k >= 3) {
       const int64_t rows2 = std::min<int64_t>(cap2, std::max<int64_t>(G->m, 1));
       W->rows2.ensure((size_t)rows2 * 2 * sizeof(int32_t), stream);
-      M.ensure_depth(2, rows2);
     }
     // The plan goes through pinned memory so the copy is truly asynchronous.
     *W->host_plan = plan;
