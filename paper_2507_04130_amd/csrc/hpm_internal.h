@@ -25,10 +25,6 @@ constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
 constexpr int kFilterMinLen = 256;    // pivot lists at least this long are pre-filtered
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 
-// Per-vertex validator flags: bit p set when the vertex may be the image of
-// pattern position p (k <= 16 positions).
-using vflag_t = uint16_t;
-
 // Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.
 struct DevGraph {
   int32_t n;
@@ -43,6 +39,7 @@ struct DevGraph {
   int32_t n_vcols, n_ecols;
   const int32_t* vcol[kMaxCols];  // [n] each
   const int32_t* ecol[kMaxCols];  // [m] each, out-CSR order
+  const int32_t* ecol_in[kMaxCols];  // [m] each, the same columns in in-CSR order
 };
 
 // Matching plan in "position" space: position p holds original pattern vertex
@@ -90,9 +87,13 @@ hipError_t launch_transpose_ids(const int32_t* in_off, const int32_t* in_nbrs,
 hipError_t launch_reverse_ids(const int32_t* out_off, const int32_t* out_nbrs, const int32_t* src,
                               int32_t m, int32_t* rev_eid, hipStream_t stream);
 
-// bits0/bits1: bitmaps of flag bits 0 and 1, 2*ceil(n/64) words each.
-hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
-                                   uint32_t* bits0, uint32_t* bits1, hipStream_t stream);
+// col_in[j] = col[in_eid[j]]: an arc column copied into in-CSR order.
+hipError_t launch_columns_in_order(const int32_t* col, const int32_t* in_eid, int32_t m,
+                                   int32_t* col_in, hipStream_t stream);
+// vbits: one bitmap per pattern position (position p at vbits + p * words,
+// words = 2 * ceil(n / 64)); bit v set when v passes that position's validator.
+hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint32_t* vbits,
+                                   int64_t words, hipStream_t stream);
 // out_mode 0: depth-2 rows [.][2] in position order, written into per-block
 //   regions of `out` (rows indexed like the chunk's arcs), per-block counts to
 //   blk_count[grid]; compact them with launch_rows2_compact + _gather.
@@ -124,7 +125,8 @@ hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
 hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream_t stream);
 // out_mode: 0 write depth d+1 rows; 1 count only; 2 count and write final rows.
 // fpool: pre-filtered candidate lists (rows whose pivot code has bit 1 set).
-hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
+// abits: the validator bitmap of position d.
+hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
                          int out_mode, int32_t* out, unsigned long long* cursor,
@@ -140,7 +142,7 @@ hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r,
                               unsigned long long* keys, uint32_t H, int32_t* dense,
                               unsigned long long* slot_key, int64_t* slot_region,
                               unsigned long long* counters, hipStream_t stream);
-hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
+hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                                int32_t a, int32_t nslots, const unsigned long long* slot_key,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                hipStream_t stream);

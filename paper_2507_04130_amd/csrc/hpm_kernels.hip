@@ -57,6 +57,22 @@ __device__ __forceinline__ bool arc_ok(const DevGraph& g, const DevPlan* __restr
   return ok;
 }
 
+// Same predicate for the arc at in-CSR position j (columns stored in in-CSR order).
+__device__ __forceinline__ bool arc_ok_in(const DevGraph& g, const DevPlan* __restrict__ P, int p,
+                                          int q, int32_t j) {
+  const uint32_t mask = P->amask[p][q];
+  if (mask == 0) return true;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < kMaxCols; ++c) {
+    if (mask & (1u << c)) {
+      const int32_t x = g.ecol_in[c][j];
+      ok = ok && x >= P->alo[p][q][c] && x <= P->ahi[p][q][c];
+    }
+  }
+  return ok;
+}
+
 // Index of key in the ascending run a[lo, hi), or -1.
 __device__ __forceinline__ int32_t find_in(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
                                            int32_t key) {
@@ -264,19 +280,26 @@ __global__ __launch_bounds__(kBlock) void k_reverse_ids(const int32_t* __restric
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_columns_in_order(const int32_t* __restrict__ col,
+                                                             const int32_t* __restrict__ in_eid,
+                                                             int32_t m, int32_t* __restrict__ col_in) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * kBlock)
+    col_in[j] = col[in_eid[j]];
+}
+
 // ------------------------------------------------------------ vertex validator
 
 __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
                                                              const DevPlan* __restrict__ P,
-                                                             vflag_t* __restrict__ vflag,
-                                                             uint32_t* __restrict__ bits0,
-                                                             uint32_t* __restrict__ bits1) {
-  // Bit p of vflag[v]: v passes the vertex validator for pattern position p
-  // (predicates and in/out degree at least the pattern's).  Alg. 2 states it
-  // for position 0 and Alg. 3 applies it to position 1; the same test is a
-  // sound filter for every later position, so it is computed once per vertex.
-  // Bits 0 and 1 are also packed into bitmaps (one bit per vertex) for the
-  // arc scan, whose random tests of arc heads then stay in L2.
+                                                             uint32_t* __restrict__ vbits,
+                                                             int64_t words) {
+  // Bit v of bitmap p (vbits + p * words): v passes the vertex validator for
+  // pattern position p (predicates and in/out degree at least the pattern's).
+  // Alg. 2 states it for position 0 and Alg. 3 applies it to position 1; the
+  // same test is a sound filter for every later position, so it is computed
+  // once per vertex.  One bit per vertex keeps each position's flags small
+  // enough (n/8 bytes) to stay in L2 while kernels test random vertices.
   const int32_t k = P->k;
   uint32_t cols = 0;
   for (int p = 0; p < k; ++p) cols |= P->vmask[p];
@@ -299,15 +322,14 @@ __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
           if ((mask >> c) & 1u) ok = ok && x[c] >= P->vlo[p][c] && x[c] <= P->vhi[p][c];
         f |= (uint32_t)ok << p;
       }
-      vflag[v] = (vflag_t)f;
     }
-    const uint64_t b0 = __ballot((f & 1u) != 0);
-    const uint64_t b1 = __ballot((f & 2u) != 0);
-    if (lane == 0) {  // base is a multiple of 64: two whole words per bitmap
-      bits0[base >> 5] = (uint32_t)b0;
-      bits0[(base >> 5) + 1] = (uint32_t)(b0 >> 32);
-      bits1[base >> 5] = (uint32_t)b1;
-      bits1[(base >> 5) + 1] = (uint32_t)(b1 >> 32);
+    for (int p = 0; p < k; ++p) {
+      const uint64_t bp = __ballot(((f >> p) & 1u) != 0);
+      if (lane == 0) {  // base is a multiple of 64: two whole words
+        uint32_t* w = vbits + p * words + (base >> 5);
+        w[0] = (uint32_t)bp;
+        w[1] = (uint32_t)(bp >> 32);
+      }
     }
   }
 }
@@ -633,7 +655,7 @@ __device__ __forceinline__ bool tile_bitmap(int32_t cmin, int32_t cmax) {
 
 template <int OUT>
 __global__ __launch_bounds__(kBlock) void k_expand(
-    DevGraph g, const DevPlan* __restrict__ P, const vflag_t* __restrict__ vflag, int32_t d,
+    DevGraph g, const DevPlan* __restrict__ P, const uint32_t* __restrict__ abits, int32_t d,
     const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
     const int2* __restrict__ piv, const int32_t* __restrict__ fpool, int32_t r, int64_t w_begin,
     int64_t w_end, int32_t* __restrict__ out, unsigned long long* __restrict__ cursor,
@@ -804,13 +826,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(
 
       // vertex validator for position a (predicates, degrees); a pre-filtered
       // list holds only candidates that passed it and the pivot-arc predicate
-      bool ok = valid && (filtered || ((vflag[c] >> a) & 1u) != 0);
+      bool ok = valid && (filtered || ((abits[c >> 5] >> (c & 31)) & 1u) != 0);
       // predicate of the pivot arc itself
       if (ok && !filtered) {
         if (via_out) {
           if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
         } else if (P->amask[a][b]) {
-          ok = arc_ok(g, P, a, b, g.in_eid[pos]);
+          ok = arc_ok_in(g, P, a, b, pos);
         }
       }
       for (int q = 0; q < d && ok; ++q) ok = rowv(q) != c;  // injectivity
@@ -838,7 +860,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
             if (arc_out ? !(q == b0 && !vo0) : iso) {
               const int32_t e = wave_member(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c,
                                             cmin, cmax, ok, wl, lane);
-              if (ok) ok = arc_out ? (e >= 0 && arc_ok(g, P, a, q, g.in_eid[e])) : e < 0;
+              if (ok) ok = arc_out ? (e >= 0 && arc_ok_in(g, P, a, q, e)) : e < 0;
             }
           }
         } else {
@@ -858,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
             if ((bw >> q) & 1u) {
               if (!(q == b && !via_out)) {
                 const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
-                ok = e >= 0 && arc_ok(g, P, a, q, g.in_eid[e]);
+                ok = e >= 0 && arc_ok_in(g, P, a, q, e);
               }
             } else if (iso) {
               ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
@@ -894,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
           for (int32_t x = wlo + threadIdx.x; x < whi; x += kBlock) {
             const int32_t e = lst[x] - cmin;
             bool pass = true;
-            if (need) pass = in_dir ? arc_ok(g, P, a, q, g.in_eid[x]) : arc_ok(g, P, q, a, x);
+            if (need) pass = in_dir ? arc_ok_in(g, P, a, q, x) : arc_ok(g, P, q, a, x);
             if (pass) atomicOr(&bm[e >> 5], 1u << (e & 31));
           }
           __syncthreads();
@@ -924,8 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
               else if (!need)
                 ok = pos >= 0;
               else
-                ok = pos >= 0 && (in_dir ? arc_ok(g, P, a, q, g.in_eid[pos])
-                                         : arc_ok(g, P, q, a, pos));
+                ok = pos >= 0 && (in_dir ? arc_ok_in(g, P, a, q, pos) : arc_ok(g, P, q, a, pos));
               if (!ok) keep &= ~(1u << it);
             }
           }
@@ -1047,7 +1068,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
 // One block per distinct list: order-preserving compaction of the candidates
 // that pass the vertex validator of position a and the pivot-arc predicate.
 __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
-                                                         const vflag_t* __restrict__ vflag,
+                                                         const uint32_t* __restrict__ abits,
                                                          int32_t a,
                                                          const unsigned long long* __restrict__ slot_key,
                                                          const int64_t* __restrict__ slot_region,
@@ -1069,8 +1090,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
     bool ok = false;
     if (x < hi) {
       c = lst[x];
-      ok = ((vflag[c] >> a) & 1u) != 0;
-      if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok(g, P, a, b, g.in_eid[x]);
+      ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
+      if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok_in(g, P, a, b, x);
     }
     int32_t tot;
     const int32_t ex = block_exclusive_scan<int32_t>(ok ? 1 : 0, s_scan, &tot);
@@ -1198,11 +1219,19 @@ int64_t edge_scan_blocks(int64_t arcs) {
   return t < 1 ? 1 : t;
 }
 
-hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, vflag_t* vflag,
-                                   uint32_t* bits0, uint32_t* bits1, hipStream_t stream) {
+hipError_t launch_columns_in_order(const int32_t* col, const int32_t* in_eid, int32_t m,
+                                   int32_t* col_in, hipStream_t stream) {
+  if (m <= 0) return hipSuccess;
+  k_columns_in_order<<<grid_for(m, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(col, in_eid, m,
+                                                                                 col_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint32_t* vbits,
+                                   int64_t words, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
-  k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan, vflag,
-                                                                                   bits0, bits1);
+  k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan, vbits,
+                                                                                   words);
   return hipGetLastError();
 }
 
@@ -1271,7 +1300,7 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag, int32_t d,
+hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
                          int out_mode, int32_t* out, unsigned long long* cursor,
@@ -1280,15 +1309,15 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const vflag_t* 
   if (w_end <= w_begin || r <= 0) return hipSuccess;
   switch (out_mode) {
     case 0:
-      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
                                                w_begin, w_end, out, cursor, out_cap, partials);
       break;
     case 1:
-      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
                                                w_begin, w_end, out, cursor, out_cap, partials);
       break;
     default:
-      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, vflag, d, rows, off, piv, fpool, r,
+      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
                                                w_begin, w_end, out, cursor, out_cap, partials);
       break;
   }
@@ -1310,12 +1339,12 @@ hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r,
   return hipGetLastError();
 }
 
-hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const vflag_t* vflag,
+hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                                int32_t a, int32_t nslots, const unsigned long long* slot_key,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
-  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, vflag, a, slot_key, slot_region, pool,
+  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, abits, a, slot_key, slot_region, pool,
                                                 fcount);
   return hipGetLastError();
 }

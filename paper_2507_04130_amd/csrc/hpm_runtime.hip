@@ -95,7 +95,7 @@ struct DevBuf {
 // Per-call scratch.  Pooled per graph so that concurrent calls (different
 // streams) never share one, and repeated calls reuse allocations.
 struct Workspace {
-  DevBuf plan, vflag, vbits, counters, partials, blkcount, blkprefix, rows2, rows2d;
+  DevBuf plan, vbits, counters, partials, blkcount, blkprefix, rows2, rows2d;
   DevBuf off[kMaxK], piv[kMaxK], bsum[kMaxK], rows[kMaxK];
   // pivot-list filter: per depth the filtered lists and the rows' new prefix
   // sums; shared by all depths the hash table and slot descriptors
@@ -110,7 +110,7 @@ struct Workspace {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
   size_t held() const {
-    size_t s = plan.bytes + vflag.bytes + vbits.bytes + counters.bytes + partials.bytes +
+    size_t s = plan.bytes + vbits.bytes + counters.bytes + partials.bytes +
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
     for (int d = 0; d < kMaxK; ++d)
@@ -119,7 +119,7 @@ struct Workspace {
     return s;
   }
   void release_all() {
-    plan.release(); vflag.release(); vbits.release(); counters.release(); partials.release();
+    plan.release(); vbits.release(); counters.release(); partials.release();
     blkcount.release(); blkprefix.release(); rows2.release(); rows2d.release();
     fkeys.release(); fdense.release(); fslot_key.release(); fslot_region.release();
     fcount.release();
@@ -139,7 +139,7 @@ struct hpm_graph {
   int64_t m = 0;
   int32_t n_vcols = 0, n_ecols = 0;
   DevBuf out_off, out_nbrs, in_off, in_nbrs, src, in_eid, rev_eid;
-  DevBuf vcols[kMaxCols], ecols[kMaxCols];
+  DevBuf vcols[kMaxCols], ecols[kMaxCols], ecols_in[kMaxCols];
   std::mutex mu;
   std::vector<Workspace*> pool;
 
@@ -149,7 +149,7 @@ struct hpm_graph {
   uint64_t bytes() const {
     uint64_t s = out_off.bytes + out_nbrs.bytes + in_off.bytes + in_nbrs.bytes + src.bytes +
                  in_eid.bytes + rev_eid.bytes;
-    for (int c = 0; c < kMaxCols; ++c) s += vcols[c].bytes + ecols[c].bytes;
+    for (int c = 0; c < kMaxCols; ++c) s += vcols[c].bytes + ecols[c].bytes + ecols_in[c].bytes;
     return s;
   }
   DevGraph view() const {
@@ -168,6 +168,7 @@ struct hpm_graph {
     for (int c = 0; c < kMaxCols; ++c) {
       g.vcol[c] = vcols[c].as<int32_t>();
       g.ecol[c] = ecols[c].as<int32_t>();
+      g.ecol_in[c] = ecols_in[c].as<int32_t>();
     }
     return g;
   }
@@ -415,8 +416,9 @@ struct Matcher {
 
   DevPlan* dplan() const { return W->plan.as<DevPlan>(); }
   int64_t bit_words() const { return (G->n + 63) / 64 * 2; }
-  uint32_t* bits0() const { return W->vbits.as<uint32_t>(); }
-  uint32_t* bits1() const { return W->vbits.as<uint32_t>() + bit_words(); }
+  uint32_t* bits(int p) const { return W->vbits.as<uint32_t>() + p * bit_words(); }
+  uint32_t* bits0() const { return bits(0); }
+  uint32_t* bits1() const { return bits(1); }
   unsigned long long* counters() const { return W->counters.as<unsigned long long>(); }
 
   hipEvent_t event() {
@@ -527,7 +529,7 @@ struct Matcher {
     W->off2[d].ensure((size_t)(r + 1) * 8, stream);
     int64_t* off2 = W->off2[d].as<int64_t>();
     launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_lists(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, (int32_t)nslots,
+      return hpm::launch_filter_lists(g, dplan(), bits(d), d, (int32_t)nslots,
                                       W->fslot_key.as<unsigned long long>(),
                                       W->fslot_region.as<int64_t>(), W->fpool[d].as<int32_t>(),
                                       W->fcount.as<int32_t>(), stream);
@@ -568,7 +570,7 @@ struct Matcher {
       const int grid = grid_for(work, hpm::kExpandTile);
       const int mode = maps ? 2 : 1;
       launch(HPM_K_LAST_LEVEL, [&] {
-        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, offp, piv,
+        return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
                                   fpool, (int32_t)r, 0, work, mode, maps, counters() + kCntEmit,
                                   maps ? cap : 0, W->partials.as<unsigned long long>(), grid,
                                   stream);
@@ -591,7 +593,7 @@ struct Matcher {
       zero_counter(kCntCursor);
       const int grid = grid_for(n_items, hpm::kExpandTile);
       launch(HPM_K_EXPAND, [&] {
-        return hpm::launch_expand(g, dplan(), W->vflag.as<hpm::vflag_t>(), d, rows, offp, piv,
+        return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
                                   fpool, (int32_t)r, w0, w1, 0, out, counters() + kCntCursor,
                                   (unsigned long long)n_items,
                                   W->partials.as<unsigned long long>(), grid, stream);
@@ -606,8 +608,8 @@ struct Matcher {
     const int64_t m = G->m;
     st.arcs_scanned = (uint64_t)m;
     launch(HPM_K_VERTEX_VALIDATOR, [&] {
-      return hpm::launch_vertex_validator(g, dplan(), W->vflag.as<hpm::vflag_t>(), bits0(),
-                                          bits1(), stream);
+      return hpm::launch_vertex_validator(g, dplan(), W->vbits.as<uint32_t>(), bit_words(),
+                                          stream);
     });
     if (k == 2) {
       const int grid = grid_for(m, hpm::kScanTile);
@@ -770,10 +772,16 @@ int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_o
     hip_check(hipMemcpyAsync(&bits, e, sizeof(bits), hipMemcpyDeviceToHost, stream), "readback");
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (bits) fail(HPM_E_GRAPH, graph_error_text(bits));
-    // only on a valid graph: every head indexes out_off
+    // only on a valid graph: every head indexes out_off, every in_eid is an arc
     hip_check(hpm::launch_reverse_ids(G->out_off.as<int32_t>(), G->out_nbrs.as<int32_t>(),
                                       G->src.as<int32_t>(), mi, G->rev_eid.as<int32_t>(), stream),
               "reverse ids");
+    for (int c = 0; c < n_ecols; ++c) {
+      G->ecols_in[c].ensure(mb ? mb : 4, stream);
+      hip_check(hpm::launch_columns_in_order(G->ecols[c].as<int32_t>(), G->in_eid.as<int32_t>(),
+                                             mi, G->ecols_in[c].as<int32_t>(), stream),
+                "columns in in-CSR order");
+    }
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     *out = G.release();
     return HPM_OK;
@@ -867,8 +875,7 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     // region 8, dense row 8, prefix 8, pivot 8, per-tile counts and block
     // sums); depth d >= 3 costs 4d + 17 B per row.
     const int max_grid = std::max(64, G->num_cus * 8);
-    const uint64_t fixed = sizeof(DevPlan) + (uint64_t)G->n * sizeof(hpm::vflag_t) +
-                           ((uint64_t)G->n + 63) / 64 * 16 + 64 +
+    const uint64_t fixed = sizeof(DevPlan) + ((uint64_t)G->n + 63) / 64 * 8 * (uint64_t)k + 64 +
                            (uint64_t)max_grid * 2 * sizeof(unsigned long long) + 4096;
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
@@ -924,8 +931,7 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     M.chunk = chunk;
     M.budget = budget;
     W->plan.ensure(sizeof(DevPlan), stream);
-    W->vflag.ensure((size_t)std::max<int32_t>(G->n, 1) * sizeof(hpm::vflag_t), stream);
-    W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * 2 * sizeof(uint32_t), stream);
+    W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);
     W->partials.ensure((size_t)max_grid * sizeof(unsigned long long), stream);
     if (k >= 3) {
