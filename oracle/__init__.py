@@ -50,8 +50,8 @@ def _load():
     lib.og_match.restype = ctypes.c_int
     lib.og_match.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, ctypes.c_int32, P,
                              ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
-                             ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32,
-                             ctypes.POINTER(_Result)]
+                             ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_uint64,
+                             ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Result)]
     lib.og_free.argtypes = [P]
     lib.og_sort_rows.argtypes = [P, ctypes.c_uint64, ctypes.c_int32]
     lib.og_fingerprint.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, P]
@@ -68,20 +68,25 @@ def _c32(a):
 
 
 class OracleResult:
-    def __init__(self, count, fp, rows, seconds, threads):
+    def __init__(self, count, fp, rows, seconds, threads, tested=0, capped=False):
         self.count = count
+        self.tested = tested      # candidate images tested (all depths, roots included)
+        self.capped = capped      # the max_tested bound was passed: count is None
         self.fingerprint = fp
         self.rows = rows
         self.seconds = seconds
         self.threads = threads
 
 
-def match(g, p, mode: int, threads: int = 1, rows: bool = True, root_mask=None) -> OracleResult:
+def match(g, p, mode: int, threads: int = 1, rows: bool = True, root_mask=None,
+          max_tested: int = 0) -> OracleResult:
     """All embeddings of pattern p in graph g (mode 0 = induced iso, 1 = mono).
 
     g: synth.graphs.HostGraph; p: synth.patterns.Pattern.  rows=True returns the
     sorted int32 [count, k] array (original pattern ids).  root_mask: optional
     uint8[n]; only embeddings with f(0) in the mask are enumerated.
+    max_tested: if nonzero, the search stops once it has tested more candidate
+    images than this; the result then has capped=True and count None.
     """
     lib = _load()
     out_off = np.ascontiguousarray(g.out_off, dtype=np.int64)
@@ -97,12 +102,16 @@ def match(g, p, mode: int, threads: int = 1, rows: bool = True, root_mask=None) 
         raise ValueError("pattern predicate arrays do not match the graph's column counts")
     mask = None if root_mask is None else np.ascontiguousarray(root_mask, dtype=np.uint8)
     res = _Result()
+    tested = ctypes.c_uint64(0)
     t0 = time.perf_counter()
     rc = lib.og_match(g.n, g.m, _p(out_off), _p(out_nbrs), _p(in_off), _p(in_nbrs), nv, _p(vcols),
                       ne, _p(ecols), p.k, p.n_arcs, _p(src), _p(dst), _p(vop), _p(vval), _p(eop),
                       _p(evl), int(mode), int(threads), _p(mask), int(bool(rows)),
-                      ctypes.byref(res))
+                      int(max_tested), ctypes.byref(tested), ctypes.byref(res))
     dt = time.perf_counter() - t0
+    nthr = threads if threads > 0 else os.cpu_count()
+    if rc == 1:
+        return OracleResult(None, None, None, dt, nthr, int(tested.value), True)
     if rc != 0:
         raise RuntimeError(f"og_match failed: {rc}")
     out_rows = None
@@ -112,8 +121,8 @@ def match(g, p, mode: int, threads: int = 1, rows: bool = True, root_mask=None) 
         out_rows = (buf[: cnt * p.k].reshape(cnt, p.k).copy() if cnt
                     else np.zeros((0, p.k), dtype=np.int32))
         lib.og_free(ctypes.cast(res.rows, ctypes.c_void_p))
-    return OracleResult(int(res.count), (int(res.fp1), int(res.fp2)), out_rows, dt,
-                        threads if threads > 0 else os.cpu_count())
+    return OracleResult(int(res.count), (int(res.fp1), int(res.fp2)), out_rows, dt, nthr,
+                        int(tested.value))
 
 
 def sort_rows(rows: np.ndarray) -> np.ndarray:

@@ -33,6 +33,8 @@
 #include <vector>
 #include <omp.h>
 
+#include <atomic>
+
 namespace {
 
 struct Graph {
@@ -141,6 +143,14 @@ struct Search {
   std::vector<int32_t> f;       // f[pattern vertex] = target vertex (valid when mapped)
   uint64_t count = 0;
   uint64_t fp1 = 0, fp2 = 0;    // running fingerprint of the rows found
+  // Optional bound on the search: every candidate image tested at any depth
+  // (roots included) is one step; local tallies are flushed into *shared
+  // every kFlush steps and the search stops once the shared total passes cap
+  // (0 = unbounded).
+  static constexpr uint64_t kFlush = 1 << 14;
+  uint64_t cap = 0, tested = 0, unflushed = 0;
+  std::atomic<uint64_t>* shared = nullptr;
+  std::atomic<bool>* stop = nullptr;
   std::vector<int32_t> rows;    // flattened [count][k], original pattern order
 
   Search(const Graph& g_, const Pattern& p_, const Plan& pl_, int mode_, bool keep)
@@ -213,10 +223,23 @@ struct Search {
   }
 
   void try_candidate(int32_t d, int32_t a, int32_t c) {
+    if (cap && stop->load(std::memory_order_relaxed)) return;
+    tally();
     if (!feasible(d, a, c)) return;
     f[a] = c;
     extend(d + 1);
     f[a] = -1;
+  }
+
+  void tally() {
+    ++tested;
+    if (!cap || ++unflushed < kFlush) return;
+    flush();
+  }
+
+  void flush() {
+    if (shared->fetch_add(unflushed) + unflushed > cap) stop->store(true);
+    unflushed = 0;
   }
 };
 
@@ -251,34 +274,54 @@ typedef struct {
 // g_*: host CSR arrays as described on the Graph struct above.  root_mask: NULL
 // (all roots) or uint8[n]; when given, only embeddings whose image of the first
 // breadth-first vertex (pattern vertex 0 for a connected pattern) has a nonzero
-// mask entry are enumerated.  Returns 0, or -1 on bad arguments.
+// mask entry are enumerated.  max_tested: 0, or a bound on the number of
+// candidate images (one target vertex for one pattern vertex, roots included)
+// the search may test; the total tested is written to *tested when non-NULL.
+// Returns 0; 1 when the bound was passed (count and rows are then not valid;
+// the decision depends only on the total, not on thread timing); -1 on bad
+// arguments.
 int og_match(int32_t n, int64_t m, const int64_t* out_off, const int32_t* out_nbrs,
              const int64_t* in_off, const int32_t* in_nbrs, int32_t n_vcols, const int32_t* vcols,
              int32_t n_ecols, const int32_t* ecols, int32_t k, int32_t n_arcs, const int32_t* src,
              const int32_t* dst, const int32_t* vop, const int32_t* vval, const int32_t* eop,
              const int32_t* eval, int32_t mode, int32_t n_threads, const uint8_t* root_mask,
-             int32_t keep_rows, og_result* res) {
+             int32_t keep_rows, uint64_t max_tested, uint64_t* tested, og_result* res) {
   if (!res || k < 1 || n < 0 || m < 0) return -1;
+  std::atomic<uint64_t> shared_tested{0};
+  std::atomic<bool> stop{false};
   Graph g{n, m, out_off, out_nbrs, in_off, in_nbrs, n_vcols, vcols, n_ecols, ecols};
   Pattern p{k, n_arcs, src, dst, vop, vval, eop, eval};
   Plan pl = make_plan(p);
   int32_t root = pl.order[0];
   if (n_threads <= 0) n_threads = omp_get_max_threads();
   std::vector<Search*> per(n_threads, nullptr);
-  uint64_t total = 0, fp1 = 0, fp2 = 0;
-#pragma omp parallel num_threads(n_threads) reduction(+ : total, fp1, fp2)
+  uint64_t total = 0, fp1 = 0, fp2 = 0, n_tested = 0;
+#pragma omp parallel num_threads(n_threads) reduction(+ : total, fp1, fp2, n_tested)
   {
     int tid = omp_get_thread_num();
     Search* s = new Search(g, p, pl, mode, keep_rows != 0);
+    s->cap = max_tested;
+    s->shared = &shared_tested;
+    s->stop = &stop;
     per[tid] = s;
 #pragma omp for schedule(dynamic, 16)
     for (int32_t x = 0; x < n; ++x) {
       if (root_mask && !root_mask[x]) continue;
       s->try_candidate(0, root, x);
     }
+    if (max_tested) s->flush();
     total += s->count;
     fp1 += s->fp1;
     fp2 += s->fp2;
+    n_tested += s->tested;
+  }
+  if (tested) *tested = n_tested;
+  if (max_tested && (stop.load() || n_tested > max_tested)) {
+    for (Search* s : per) delete s;
+    res->count = 0;
+    res->fp1 = res->fp2 = 0;
+    res->rows = nullptr;
+    return 1;
   }
   res->count = total;
   res->fp1 = fp1;

@@ -213,3 +213,21 @@ def test_fingerprint_is_order_independent():
     assert fp != oracle.fingerprint(rows2)
     rows3 = rows[:, [1, 0, 2, 3]]
     assert fp != oracle.fingerprint(rows3)
+
+
+@pytest.mark.parametrize("n,k,threads", [(7, 4, 1), (9, 3, 3), (6, 5, 2)])
+def test_search_bound_on_complete_digraph(n, k, threads):
+    """In a complete digraph every vertex has n-1 out- and in-neighbours and
+    every injective partial map of a connected pattern is feasible under
+    monomorphism, so the search tests n roots plus n-1 candidates under each of
+    the n!/(n-d)! maps at depths 1..k-1; a bound one below that total stops
+    it, the exact total does not."""
+    g = complete_digraph(n)
+    p = make_pattern(k, [(i, i + 1) for i in range(k - 1)])
+    want = n + (n - 1) * sum(pins.falling(n, d) for d in range(1, k))
+    full = oracle.match(g, p, MONO, threads=threads, rows=False)
+    assert full.tested == want and full.count == pins.falling(n, k)
+    at = oracle.match(g, p, MONO, threads=threads, rows=False, max_tested=want)
+    assert not at.capped and at.count == full.count and at.tested == want
+    below = oracle.match(g, p, MONO, threads=threads, rows=False, max_tested=want - 1)
+    assert below.capped and below.count is None
