@@ -162,6 +162,25 @@ int hpm_match(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* str
               const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap);
 
 /*
+ * hpm_match_batch -- count the embeddings of n patterns in one resident graph.
+ *
+ * patterns[i] is matched in mode modes[i] (HPM_ISO or HPM_MONO) exactly as
+ * hpm_match would, counts only: counts[i] and status[i] (HPM_OK or an error
+ * code of hpm_match) are written for every i.  The patterns are spread over
+ * `workers` host threads (0 = 4), each driving its own non-blocking HIP stream
+ * with its own scratch (opts->hbm_budget_bytes, or its default, is divided
+ * among them), so the device works on several patterns at once.  Work already
+ * queued on `stream` completes first; the call returns when all patterns are
+ * done.  Returns HPM_OK, or the status of the first failed pattern (the
+ * others are still matched).  This is the batched form of the edge-centric
+ * search: many small queries sharing one graph (Sec. IV-B uses patterns of
+ * 3 to 20 vertices).
+ */
+int hpm_match_batch(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
+                    const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                    int32_t workers, uint64_t* counts, int32_t* status);
+
+/*
  * hpm_plan_order -- the matching order hpm_match would use (host only, no device).
  *
  * order[pos] receives the original pattern vertex placed at position pos

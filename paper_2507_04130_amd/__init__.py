@@ -6,4 +6,5 @@ thin ctypes binding.
 """
 from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_FILTER, F_NO_REORDER, F_TIMING, Graph,  # noqa: F401
                   HpmError,
-                  abi_version, last_stats, load, match, plan_order, status_string)
+                  abi_version, last_stats, load, match, match_batch, plan_order,
+                  status_string)

@@ -22,7 +22,7 @@ constexpr int kLdsRowInts = 1024;     // partial-mapping entries staged in LDS p
 constexpr int kTilePool = 2048;       // LDS entries for staged adjacency lists per block
 constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront stages
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
-constexpr int kFilterMinLen = 256;    // pivot lists at least this long are pre-filtered
+constexpr int kFilterMinLen = 32;     // pivot lists at least this long are pre-filtered
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 
 // Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.

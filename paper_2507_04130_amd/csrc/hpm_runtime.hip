@@ -9,7 +9,9 @@
 #include <climits>
 #include <cstring>
 #include <memory>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -521,7 +523,9 @@ struct Matcher {
     sync();
     const int64_t nslots = (int64_t)W->host[kCntFilterSlots];
     const int64_t pool = (int64_t)W->host[kCntFilterPool];
-    if (nslots == 0 || pool >= INT32_MAX) return;
+    // Filtering reads every distinct list once more; it pays when the lists
+    // are shared, i.e. their total length is well below the depth's work.
+    if (nslots == 0 || pool >= INT32_MAX || 2 * pool > *work) return;
     const uint64_t more = (uint64_t)pool * 4 + (uint64_t)nslots * 4 + (uint64_t)(r + 1) * 8;
     if (W->held() + more > budget) return;
     W->fpool[d].ensure((size_t)std::max<int64_t>(pool, 1) * 4, stream);
@@ -830,21 +834,17 @@ int hpm_last_stats(hpm_match_stats* out) {
   });
 }
 
-int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream_,
-              const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap) {
-  return guarded([&]() -> int {
+}  // extern "C"
+
+namespace {
+
+// One match, as documented on hpm_match; throws Failure.  Returns HPM_OK or
+// HPM_E_TRUNCATED (count valid).
+int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, uint32_t flags,
+              uint64_t budget, uint64_t* count, int32_t* mappings, uint64_t cap,
+              hpm_match_stats* stats) {
     const auto t0 = std::chrono::steady_clock::now();
-    if (!gc) fail(HPM_E_ARG, "graph is NULL");
-    if (!count) fail(HPM_E_ARG, "count is NULL");
     if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
-    uint32_t flags = 0;
-    uint64_t budget = 0;
-    if (opts) {
-      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
-      flags = opts->flags;
-      budget = opts->hbm_budget_bytes;
-    }
-    hpm_graph* G = const_cast<hpm_graph*>(gc);
     PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
     const int32_t k = info.k;
     if (mappings && cap > (uint64_t)INT64_MAX / (uint64_t)k) fail(HPM_E_ARG, "cap too large");
@@ -862,7 +862,6 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
         if (prev != want) (void)hipSetDevice(prev);
       }
     } dg(cur, G->device);
-    hipStream_t stream = static_cast<hipStream_t>(stream_);
 
     if (budget == 0) {
       size_t free_b = 0, total_b = 0;
@@ -953,12 +952,94 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     M.st.ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *count = M.st.count;
-    t_stats = M.st;
+    if (stats) *stats = M.st;
     (void)emitted;
     if (mappings && M.st.count > cap) {
       t_error = "count " + std::to_string(M.st.count) + " exceeds cap " + std::to_string(cap);
       return HPM_E_TRUNCATED;
     }
+    return HPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
+              const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap) {
+  return guarded([&]() -> int {
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (!count) fail(HPM_E_ARG, "count is NULL");
+    uint32_t flags = 0;
+    uint64_t budget = 0;
+    if (opts) {
+      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
+      flags = opts->flags;
+      budget = opts->hbm_budget_bytes;
+    }
+    return match_one(const_cast<hpm_graph*>(gc), p, (int)mode, static_cast<hipStream_t>(stream),
+                     flags, budget, count, mappings, cap, &t_stats);
+  });
+}
+
+int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
+                    const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                    int32_t workers, uint64_t* counts, int32_t* status) {
+  return guarded([&]() -> int {
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (n < 0 || (n > 0 && (!patterns || !modes || !counts || !status)))
+      fail(HPM_E_ARG, "NULL batch arrays");
+    if (workers < 0 || workers > 64) fail(HPM_E_ARG, "workers must be 0..64");
+    if (workers == 0) workers = 4;
+    workers = std::min<int32_t>(workers, std::max<int32_t>(n, 1));
+    uint32_t flags = 0;
+    uint64_t budget = 0;
+    if (opts) {
+      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
+      flags = opts->flags & ~(uint32_t)HPM_F_TIMING;
+      budget = opts->hbm_budget_bytes;
+    }
+    hpm_graph* G = const_cast<hpm_graph*>(gc);
+    hip_check(hipSetDevice(G->device), "hipSetDevice");
+    if (budget == 0) {
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      budget = free_b / 4;
+    }
+    const uint64_t share = budget / (uint64_t)workers;
+    // work issued on the caller's stream before the batch comes first
+    hip_check(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+    std::atomic<int32_t> next(0);
+    std::vector<std::string> errors((size_t)n);
+    auto worker = [&]() {
+      (void)hipSetDevice(G->device);
+      hipStream_t s = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+      for (int32_t i = next++; i < n; i = next++) {
+        try {
+          if (!s) fail(HPM_E_DEVICE, "hipStreamCreateWithFlags failed");
+          status[i] = match_one(G, &patterns[i], modes[i], s, flags, share, &counts[i], nullptr, 0,
+                                nullptr);
+        } catch (const Failure& f) {
+          status[i] = f.status;
+          errors[i] = f.msg;
+        } catch (const std::bad_alloc&) {
+          status[i] = HPM_E_NOMEM;
+        } catch (...) {
+          status[i] = HPM_E_INTERNAL;
+        }
+      }
+      if (s) (void)hipStreamDestroy(s);
+    };
+    std::vector<std::thread> pool;
+    for (int32_t w = 1; w < workers; ++w) pool.emplace_back(worker);
+    worker();
+    for (std::thread& t : pool) t.join();
+    for (int32_t i = 0; i < n; ++i)
+      if (status[i] != HPM_OK) {
+        t_error = "pattern " + std::to_string(i) + ": " + errors[i];
+        return status[i];
+      }
     return HPM_OK;
   });
 }

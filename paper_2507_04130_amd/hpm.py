@@ -26,7 +26,7 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
            "reduce", "filter")
 
 # Every function include/hpm.h declares.
-EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
+EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match", "hpm_match_batch",
            "hpm_plan_order", "hpm_last_stats", "hpm_status_string", "hpm_last_error",
            "hpm_abi_version")
 
@@ -85,6 +85,8 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(U64)]
     lib.hpm_match.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
                               ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
+    lib.hpm_match_batch.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
+                                    I32, P, P]
     lib.hpm_plan_order.argtypes = [ctypes.POINTER(_Pattern), I32, I32, ctypes.c_uint32, P]
     lib.hpm_last_stats.argtypes = [ctypes.POINTER(_Stats)]
     lib.hpm_status_string.argtypes = [ctypes.c_int]
@@ -92,7 +94,7 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-                 "hpm_plan_order", "hpm_last_stats"):
+                 "hpm_match_batch", "hpm_plan_order", "hpm_last_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -223,6 +225,35 @@ def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None
                        ctypes.byref(cnt), ctypes.c_void_p(buf.data_ptr()), int(cap))
     _check(st)
     return int(cnt.value), buf[: int(cnt.value)]
+
+
+def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
+                budget: int | None = None, flags: int = 0):
+    """Counts of many patterns on one graph (hpm_match_batch).
+
+    Returns (counts, statuses) as lists; raises HpmError if any pattern failed
+    (its status is in the exception's message).
+    """
+    lib = load()
+    n = len(patterns)
+    for p in patterns:
+        nv = 0 if p.vop is None else np.asarray(p.vop).shape[-1]
+        ne = 0 if p.eop is None else np.asarray(p.eop).shape[-1]
+        if (p.vop is not None and nv != g.n_vcols) or (p.eop is not None and ne != g.n_ecols):
+            raise HpmError(E_PATTERN, "pattern predicate columns do not match the graph")
+    structs = (_Pattern * max(n, 1))()
+    keep = []
+    for i, p in enumerate(patterns):
+        st, arrs = _pattern_struct(p)
+        structs[i] = st
+        keep.append(arrs)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    counts = np.zeros(max(n, 1), dtype=np.uint64)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0))
+    _check(lib.hpm_match_batch(g.handle, n, structs, _ptr(md), _stream_handle(stream),
+                               ctypes.byref(opts), int(workers), _ptr(counts), _ptr(status)))
+    return [int(c) for c in counts[:n]], [int(x) for x in status[:n]]
 
 
 def last_stats() -> dict:

@@ -318,3 +318,25 @@ def test_prefiltered_lists_change_nothing():
         assert oracle.fingerprint(r1) == want.fingerprint
         say(f"filter {name}/{mode}: count={c1} lists={hpm.last_stats()['filtered_lists']}")
     assert used > 0
+
+
+def test_batch_equals_single_and_oracle():
+    g = configs.c2_graph(scale=12)
+    dg = hpm.Graph.from_host(g)
+    rng = np.random.default_rng(77)
+    pats, modes = [], []
+    for i in range(48):
+        p = random_pattern(rng, kmin=3, kmax=8)
+        pats.append(p)
+        modes.append(ISO if i % 2 else MONO)
+    for workers in (1, 4, 7):
+        counts, status = hpm.match_batch(dg, pats, modes, workers=workers)
+        assert status == [0] * len(pats)
+        for p, m, c in zip(pats, modes, counts):
+            assert c == hpm.match(dg, p, m)[0]
+    for p, m, c in zip(pats[:16], modes[:16], counts[:16]):
+        assert c == oracle.match(g, p, m, threads=8, rows=False).count
+    # a failing pattern reports its own status and the others still run
+    bad = make_pattern(4, [(0, 1), (2, 3)], 1, 1)
+    with pytest.raises(hpm.HpmError):
+        hpm.match_batch(dg, pats[:3] + [bad], modes[:3] + [ISO], workers=2)
