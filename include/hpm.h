@@ -13,7 +13,8 @@
  *     Sec. III-C, Alg. 4) and are extended one pattern vertex at a time under
  *     the feasibility rules of the problem definition (Sec. II-A, Eq. (1)-(3)).
  *
- * All functions return an int status: HPM_OK (0) or a negative HPM_E_* code.
+ * All functions return an int status: HPM_OK (0) or a negative HPM_E_* code
+ * (hpm_server_poll may also return HPM_PENDING).
  * On error, hpm_last_error() returns a message for the calling thread.  No
  * C++ exception ever crosses this boundary.
  *
@@ -50,7 +51,8 @@ enum {
   HPM_E_OVERFLOW = -6,    /* match count does not fit in uint64                    */
   HPM_E_DEVICE = -7,      /* HIP runtime error                                     */
   HPM_E_UNSUPPORTED = -8, /* valid input beyond the library's limits (n, m >= 2^31) */
-  HPM_E_INTERNAL = -9     /* unexpected internal failure                           */
+  HPM_E_INTERNAL = -9,    /* unexpected internal failure                           */
+  HPM_PENDING = 1         /* hpm_server_poll: the query has not finished yet       */
 };
 
 typedef enum { HPM_ISO = 0, HPM_MONO = 1 } hpm_mode;
@@ -179,6 +181,79 @@ int hpm_match(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* str
 int hpm_match_batch(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
                     const int32_t* modes, void* stream, const hpm_match_opts* opts,
                     int32_t workers, uint64_t* counts, int32_t* status);
+
+/*
+ * Serving: a resident graph answering a stream of queries.
+ *
+ * A server owns `workers` host threads, each driving its own non-blocking HIP
+ * stream, and a device scratch budget.  Queries are submitted at any time and
+ * run as soon as a worker is free and the query is admitted: each query's
+ * scratch need is estimated on submission from the pattern and host-side
+ * statistics of the graph (attribute-column samples, size-biased mean degree),
+ * and it is granted that many bytes (at least min(256 MiB, budget / 2), at
+ * most budget / 2) out of a pool of budget / 2; the query then runs exactly as
+ * hpm_match with the grant as its scratch limit, so its result does not depend
+ * on the grant or on the other queries in flight.  Each worker keeps at most
+ * budget / (2 workers) of allocations between queries, so device scratch
+ * stays within the budget.  Admission is in arrival order, except that a query
+ * that does not fit may be overtaken by later ones that do, at most 32 times.
+ * Queries submitted while others run join them on the device (continuous
+ * batching); this is the served form of the edge-centric search on a large
+ * resident graph (Sec. I and Sec. IV-D: whole-brain connectomes held in
+ * memory and queried repeatedly).
+ */
+typedef struct hpm_server hpm_server; /* opaque */
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(hpm_server_opts)                              */
+  int32_t workers;           /* queries in flight at most (0 = 4, at most 64)        */
+  uint64_t hbm_budget_bytes; /* scratch of all queries together; 0 = 25% of free HBM */
+  uint32_t flags;            /* HPM_F_NO_REORDER / HPM_F_NO_FILTER for every query   */
+} hpm_server_opts;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(hpm_query_result)                              */
+  int32_t status;         /* the query's hpm_match status                          */
+  uint64_t count;         /* embeddings (valid for HPM_OK and HPM_E_TRUNCATED)     */
+  uint64_t est_bytes;     /* estimated scratch need used for admission             */
+  uint64_t granted_bytes; /* scratch limit the query ran with                      */
+  double queue_ms;        /* submission -> start on a worker (host clock)          */
+  double run_ms;          /* start -> result                                       */
+} hpm_query_result;
+
+typedef struct {
+  uint32_t struct_size;        /* sizeof(hpm_server_stats)                       */
+  int32_t workers, running, queued, peak_running;
+  uint64_t budget_bytes, grant_pool_bytes, granted_bytes, peak_granted_bytes;
+  uint64_t admitted;           /* queries started so far                         */
+} hpm_server_stats;
+
+/* Start a server on g (which must outlive it).
+ * opts NULL = defaults.  Errors: HPM_E_ARG, HPM_E_NOMEM (budget too small for
+ * one query), HPM_E_DEVICE. */
+int hpm_server_create(hpm_server** out, const hpm_graph* g, const hpm_server_opts* opts);
+
+/* Queue one query; the pattern is validated and copied (the caller may free
+ * it on return).  mappings/cap: as for hpm_match (a DEVICE buffer that must
+ * stay valid until the result is polled), or NULL.  *ticket identifies the
+ * query for hpm_server_poll.  Errors: HPM_E_ARG, HPM_E_PATTERN (the query is
+ * then not queued). */
+int hpm_server_submit(hpm_server* s, const hpm_pattern* p, hpm_mode mode, int32_t* mappings,
+                      uint64_t cap, uint64_t* ticket);
+
+/* Collect a query's result.  Returns HPM_PENDING if it has not finished and
+ * wait == 0; otherwise blocks until it has, fills *out (out->status is the
+ * query's own status; on a query error hpm_last_error() describes it) and
+ * forgets the ticket (poll each ticket to completion exactly once, from one
+ * thread).  Errors: HPM_E_ARG (NULL, unknown or already collected ticket). */
+int hpm_server_poll(hpm_server* s, uint64_t ticket, int32_t wait, hpm_query_result* out);
+
+/* Current load and admission counters. */
+int hpm_server_read_stats(hpm_server* s, hpm_server_stats* out);
+
+/* Run every query already submitted to completion, stop the workers and free
+ * the server.  Results not yet polled are discarded.  NULL is ignored. */
+int hpm_server_destroy(hpm_server* s);
 
 /*
  * hpm_plan_order -- the matching order hpm_match would use (host only, no device).

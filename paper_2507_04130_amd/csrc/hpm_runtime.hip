@@ -10,8 +10,11 @@
 #include <cstring>
 #include <memory>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -144,6 +147,11 @@ struct hpm_graph {
   DevBuf vcols[kMaxCols], ecols[kMaxCols], ecols_in[kMaxCols];
   std::mutex mu;
   std::vector<Workspace*> pool;
+  // Host-side statistics for frontier-size estimates (serving admission):
+  // sorted evenly spaced samples of every attribute column and the
+  // size-biased mean out- and in-degree (sum d^2 / sum d).
+  std::vector<int32_t> vsample[kMaxCols], esample[kMaxCols];
+  double sb_out = 0.0, sb_in = 0.0;
 
   ~hpm_graph() {
     for (Workspace* w : pool) delete w;
@@ -191,6 +199,27 @@ std::vector<int32_t> narrow_offsets(const int64_t* off, int32_t n, int64_t m, co
   }
   if (off[n] != m) fail(HPM_E_GRAPH, std::string(name) + "[n] must equal m");
   return out;
+}
+
+constexpr int64_t kSampleSize = 4096;
+
+// Sorted values at kSampleSize evenly spaced positions of a column.
+std::vector<int32_t> column_sample(const int32_t* col, int64_t len) {
+  const int64_t s = std::min<int64_t>(len, kSampleSize);
+  std::vector<int32_t> out((size_t)s);
+  for (int64_t j = 0; j < s; ++j) out[(size_t)j] = col[j * len / s];
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+double size_biased_degree(const std::vector<int32_t>& off) {
+  double s1 = 0.0, s2 = 0.0;
+  for (size_t i = 1; i < off.size(); ++i) {
+    const double d = (double)(off[i] - off[i - 1]);
+    s1 += d;
+    s2 += d * d;
+  }
+  return s1 > 0.0 ? s2 / s1 : 0.0;
 }
 
 void upload(DevBuf& b, const void* host, size_t bytes, hipStream_t stream) {
@@ -787,6 +816,10 @@ int hpm_graph_create(hpm_graph** out, int32_t n, int64_t m, const int64_t* out_o
                 "columns in in-CSR order");
     }
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    for (int c = 0; c < n_vcols; ++c) G->vsample[c] = column_sample(vcols[c], n);
+    for (int c = 0; c < n_ecols; ++c) G->esample[c] = column_sample(ecols[c], m);
+    G->sb_out = size_biased_degree(oo);
+    G->sb_in = size_biased_degree(io);
     *out = G.release();
     return HPM_OK;
   });
@@ -840,9 +873,24 @@ namespace {
 
 // One match, as documented on hpm_match; throws Failure.  Returns HPM_OK or
 // HPM_E_TRUNCATED (count valid).
+// Scratch that does not depend on the frontier: plan, per-position vertex
+// flags, counters, per-block partial counts.
+uint64_t scratch_fixed(const hpm_graph* G, int32_t k) {
+  const int max_grid = std::max(64, G->num_cus * 8);
+  return sizeof(DevPlan) + ((uint64_t)G->n + 63) / 64 * 8 * (uint64_t)k + 64 +
+         (uint64_t)max_grid * 2 * sizeof(unsigned long long) + 4096;
+}
+
+// Depth 2 costs 33 B per arc of a chunk (scan region 8, dense row 8, prefix 8,
+// pivot 8, per-tile counts and block sums); depth d >= 3 costs 4d + 17 B per
+// row of a chunk.
+constexpr uint64_t kDepth2BytesPerArc = 33;
+inline uint64_t row_bytes(int32_t d) { return 4 * (uint64_t)d + 17; }
+
+// Workspace: NULL takes one from the graph's pool (returned on exit).
 int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, uint32_t flags,
               uint64_t budget, uint64_t* count, int32_t* mappings, uint64_t cap,
-              hpm_match_stats* stats) {
+              hpm_match_stats* stats, Workspace* own = nullptr) {
     const auto t0 = std::chrono::steady_clock::now();
     if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
     PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
@@ -869,37 +917,34 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       budget = free_b / 4;
     }
 
-    // Scratch layout and its budget.  Fixed part: plan, vertex flags, counters,
-    // per-block partial counts.  Depth 2 costs 33 B per arc of a chunk (scan
-    // region 8, dense row 8, prefix 8, pivot 8, per-tile counts and block
-    // sums); depth d >= 3 costs 4d + 17 B per row.
+    // Scratch layout and its budget: the fixed part, then one arc chunk at
+    // depth 2 and one frontier chunk per deeper depth.
     const int max_grid = std::max(64, G->num_cus * 8);
-    const uint64_t fixed = sizeof(DevPlan) + ((uint64_t)G->n + 63) / 64 * 8 * (uint64_t)k + 64 +
-                           (uint64_t)max_grid * 2 * sizeof(unsigned long long) + 4096;
+    const uint64_t fixed = scratch_fixed(G, k);
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
     int64_t cap2 = 0, chunk = 0;
     if (k >= 3) {
       uint64_t per_row_deep = 0;
-      for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += 4 * (uint64_t)d + 17;
+      for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += row_bytes(d);
       const uint64_t m_round =
           ((uint64_t)G->m + hpm::kScanTile - 1) / hpm::kScanTile * hpm::kScanTile;
       uint64_t c2 = std::min<uint64_t>(std::max<uint64_t>(m_round, hpm::kScanTile),
-                                       (per_row_deep ? avail / 2 : avail) / 33);
+                                       (per_row_deep ? avail / 2 : avail) / kDepth2BytesPerArc);
       c2 = c2 / hpm::kScanTile * hpm::kScanTile;
       c2 = std::min<uint64_t>(c2, (uint64_t)INT32_MAX / hpm::kScanTile * hpm::kScanTile);
       if (c2 < (uint64_t)hpm::kScanTile) fail(HPM_E_NOMEM, "scratch budget below one arc chunk");
       cap2 = (int64_t)c2;
       if (per_row_deep) {
-        uint64_t c = (avail - c2 * 33) / per_row_deep;
+        uint64_t c = (avail - c2 * kDepth2BytesPerArc) / per_row_deep;
         c = std::min<uint64_t>(c, (uint64_t)1 << 30);
         if (c < kMinChunkRows) fail(HPM_E_NOMEM, "scratch budget below one frontier chunk");
         chunk = (int64_t)c;
       }
     }
 
-    Workspace* W = nullptr;
-    {
+    Workspace* W = own;
+    if (!W) {
       std::lock_guard<std::mutex> lk(G->mu);
       if (!G->pool.empty()) {
         W = G->pool.back();
@@ -911,10 +956,11 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       hpm_graph* G;
       Workspace* W;
       ~Return() {
+        if (!W) return;
         std::lock_guard<std::mutex> lk(G->mu);
         G->pool.push_back(W);
       }
-    } ret{G, W};
+    } ret{G, own ? nullptr : W};
     if (W->held() > budget) {
       hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
       W->release_all();
@@ -961,7 +1007,191 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     return HPM_OK;
 }
 
+// Fraction of a sorted column sample inside [lo, hi] (1 when there is no sample).
+double sample_fraction(const std::vector<int32_t>& smp, int32_t lo, int32_t hi) {
+  if (smp.empty()) return 1.0;
+  const auto a = std::lower_bound(smp.begin(), smp.end(), lo);
+  const auto b = std::upper_bound(smp.begin(), smp.end(), hi);
+  return b > a ? (double)(b - a) / (double)smp.size() : 0.0;
+}
+
+double vertex_fraction(const hpm_graph* G, const DevPlan& pl, int32_t pos) {
+  double f = 1.0;
+  for (int c = 0; c < G->n_vcols; ++c)
+    if (pl.vmask[pos] & (1u << c)) f *= sample_fraction(G->vsample[c], pl.vlo[pos][c], pl.vhi[pos][c]);
+  return f;
+}
+
+double arc_fraction(const hpm_graph* G, const DevPlan& pl, int32_t from, int32_t to) {
+  double f = 1.0;
+  for (int c = 0; c < G->n_ecols; ++c)
+    if (pl.amask[from][to] & (1u << c))
+      f *= sample_fraction(G->esample[c], pl.alo[from][to][c], pl.ahi[from][to][c]);
+  return f;
+}
+
+// Estimated scratch bytes of an unchunked run: the fixed part, the depth-2
+// area for all arcs, and per deeper depth the estimated rows times their cost.
+// Rows are estimated with independent attribute fractions from the column
+// samples: depth 2 = arcs x both endpoint fractions x the arc's fraction; each
+// further position multiplies by the size-biased mean degree (the expected
+// length of a neighbour list reached through an arc), its vertex fraction, its
+// arc fractions, and degree / n for every arc beyond the first that must exist.
+uint64_t estimate_scratch(const hpm_graph* G, const DevPlan& pl) {
+  const int32_t k = pl.k;
+  const double n = std::max(1.0, (double)G->n);
+  const double deg = std::max(1.0, 0.5 * (G->sb_out + G->sb_in));
+  double rows = (double)G->m * vertex_fraction(G, pl, 0) * vertex_fraction(G, pl, 1) *
+                (pl.mve_forward ? arc_fraction(G, pl, 0, 1) : arc_fraction(G, pl, 1, 0));
+  if (pl.rev_rule == 1) rows *= arc_fraction(G, pl, 1, 0) * std::min(1.0, deg / n);
+  double bytes = (double)scratch_fixed(G, k);
+  if (k >= 3) bytes += (double)kDepth2BytesPerArc * (double)G->m;
+  for (int32_t d = 2; d + 1 < k; ++d) {
+    double f = deg * vertex_fraction(G, pl, d);
+    int arcs = 0;
+    for (int32_t b = 0; b < d; ++b) {
+      if (pl.fwd[d] & (1u << b)) {
+        f *= arc_fraction(G, pl, b, d) * (arcs++ ? std::min(1.0, deg / n) : 1.0);
+      }
+      if (pl.bwd[d] & (1u << b)) {
+        f *= arc_fraction(G, pl, d, b) * (arcs++ ? std::min(1.0, deg / n) : 1.0);
+      }
+    }
+    rows = std::min(rows * f, 1e18);
+    bytes += (double)row_bytes(d + 1) * std::min(rows, (double)(1ull << 30));
+  }
+  return bytes >= 1.8e19 ? ~0ull : (uint64_t)bytes;
+}
+
 }  // namespace
+
+// ------------------------------------------------------------ serving
+
+// Queries are admitted in arrival order by their estimated scratch bytes
+// against a fixed budget: half of it is lent out as per-query grants (each
+// query runs with its grant as its scratch limit, so the chunked expansion
+// keeps it inside), and each worker may keep up to budget / (2 workers) of
+// allocations between queries; device scratch therefore never exceeds the
+// budget.  A query that does not fit waits while later ones that fit go
+// ahead, at most kMaxBypass times, after which it blocks the queue until it
+// fits.
+struct hpm_server {
+  struct Query {
+    uint64_t ticket = 0;
+    std::vector<int32_t> src, dst, vop, vval, eop, eval;
+    hpm_pattern p{};
+    int mode = 0;
+    int32_t* maps = nullptr;
+    uint64_t cap = 0;
+    uint64_t est = 0, grant = 0;
+    int bypassed = 0;
+    std::chrono::steady_clock::time_point t_submit;
+  };
+  struct Result {
+    bool done = false;
+    hpm_query_result r{};
+    std::string error;
+  };
+  static constexpr int kMaxBypass = 32;
+
+  hpm_graph* G = nullptr;
+  int32_t workers = 0;
+  uint32_t flags = 0;
+  uint64_t budget = 0, grant_pool = 0, keep = 0, min_grant = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<Query>> queue;
+  std::unordered_map<uint64_t, Result> results;
+  uint64_t next_ticket = 1, in_use = 0;
+  uint64_t admitted = 0, peak_in_use = 0;
+  int32_t running = 0, peak_running = 0;
+  bool stop = false;
+  std::string start_error;
+  std::vector<std::thread> threads;
+
+  // Next admissible query (caller holds mu), or null.
+  std::unique_ptr<Query> pick() {
+    for (size_t i = 0; i < queue.size(); ++i) {
+      Query& q = *queue[i];
+      if (in_use + q.grant <= grant_pool) {
+        if (i > 0) queue.front()->bypassed++;
+        std::unique_ptr<Query> out = std::move(queue[i]);
+        queue.erase(queue.begin() + (long)i);
+        return out;
+      }
+      if (i == 0 && q.bypassed >= kMaxBypass) return nullptr;
+    }
+    return nullptr;
+  }
+
+  void worker() {
+    using clock = std::chrono::steady_clock;
+    hipStream_t s = nullptr;
+    std::unique_ptr<Workspace> W(new Workspace());
+    const bool ok = hipSetDevice(G->device) == hipSuccess &&
+                    hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    for (;;) {
+      std::unique_ptr<Query> q;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] {
+          if (stop && queue.empty()) return true;
+          q = pick();
+          return q != nullptr;
+        });
+        if (!q) break;
+        in_use += q->grant;
+        peak_in_use = std::max(peak_in_use, in_use);
+        running++;
+        peak_running = std::max(peak_running, running);
+        admitted++;
+      }
+      const auto t0 = clock::now();
+      int status = HPM_OK;
+      uint64_t count = 0;
+      std::string err;
+      try {
+        if (!ok) fail(HPM_E_DEVICE, "worker stream could not be created");
+        status = match_one(G, &q->p, q->mode, s, flags, q->grant, &count, q->maps, q->cap,
+                           nullptr, W.get());
+        if (status != HPM_OK) err = t_error;
+      } catch (const Failure& f) {
+        status = f.status;
+        err = f.msg;
+      } catch (const std::bad_alloc&) {
+        status = HPM_E_NOMEM;
+        err = "host allocation failed";
+      } catch (...) {
+        status = HPM_E_INTERNAL;
+        err = "unknown internal error";
+      }
+      if (W->held() > keep) {
+        if (s) (void)hipStreamSynchronize(s);
+        W->release_all();
+      }
+      const auto t1 = clock::now();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        in_use -= q->grant;
+        running--;
+        Result& r = results[q->ticket];
+        r.done = true;
+        r.error = err;
+        r.r.struct_size = sizeof(hpm_query_result);
+        r.r.status = status;
+        r.r.count = count;
+        r.r.est_bytes = q->est;
+        r.r.granted_bytes = q->grant;
+        r.r.queue_ms = std::chrono::duration<double, std::milli>(t0 - q->t_submit).count();
+        r.r.run_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      }
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+    W.reset();
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
 
 extern "C" {
 
@@ -1040,6 +1270,144 @@ int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
         t_error = "pattern " + std::to_string(i) + ": " + errors[i];
         return status[i];
       }
+    return HPM_OK;
+  });
+}
+
+int hpm_server_create(hpm_server** out, const hpm_graph* gc, const hpm_server_opts* opts) {
+  return guarded([&]() -> int {
+    if (!out) fail(HPM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (opts && opts->struct_size < sizeof(hpm_server_opts))
+      fail(HPM_E_ARG, "opts.struct_size too small");
+    int32_t workers = opts ? opts->workers : 0;
+    if (workers < 0 || workers > 64) fail(HPM_E_ARG, "workers must be 0..64");
+    if (workers == 0) workers = 4;
+    hpm_graph* G = const_cast<hpm_graph*>(gc);
+    hip_check(hipSetDevice(G->device), "hipSetDevice");
+    uint64_t budget = opts ? opts->hbm_budget_bytes : 0;
+    if (budget == 0) {
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      budget = free_b / 4;
+    }
+    std::unique_ptr<hpm_server> S(new hpm_server());
+    S->G = G;
+    S->workers = workers;
+    S->flags = opts ? (opts->flags & ~(uint32_t)HPM_F_TIMING) : 0;
+    S->budget = budget;
+    S->grant_pool = budget / 2;
+    S->keep = budget / 2 / (uint64_t)workers;
+    S->min_grant = std::min<uint64_t>(S->grant_pool, (uint64_t)256 << 20);
+    if (S->grant_pool < scratch_fixed(G, HPM_MAX_K) + (uint64_t)hpm::kScanTile * 64)
+      fail(HPM_E_NOMEM, "serving budget too small");
+    hpm_server* raw = S.get();
+    for (int32_t w = 0; w < workers; ++w) S->threads.emplace_back([raw] { raw->worker(); });
+    *out = S.release();
+    return HPM_OK;
+  });
+}
+
+int hpm_server_submit(hpm_server* S, const hpm_pattern* p, hpm_mode mode, int32_t* mappings,
+                      uint64_t cap, uint64_t* ticket) {
+  return guarded([&]() -> int {
+    if (!S) fail(HPM_E_ARG, "server is NULL");
+    if (!ticket) fail(HPM_E_ARG, "ticket is NULL");
+    if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
+    hpm_graph* G = S->G;
+    PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
+    if (mappings && cap > (uint64_t)INT64_MAX / (uint64_t)info.k) fail(HPM_E_ARG, "cap too large");
+    std::unique_ptr<hpm_server::Query> q(new hpm_server::Query());
+    const size_t na = (size_t)p->n_arcs;
+    q->src.assign(p->src, p->src + na);
+    q->dst.assign(p->dst, p->dst + na);
+    if (p->vop) {
+      const size_t nv = (size_t)info.k * (size_t)G->n_vcols;
+      q->vop.assign(p->vop, p->vop + nv);
+      q->vval.assign(p->vval, p->vval + nv);
+    }
+    if (p->eop) {
+      const size_t ne = na * (size_t)G->n_ecols;
+      q->eop.assign(p->eop, p->eop + ne);
+      q->eval.assign(p->eval, p->eval + ne);
+    }
+    q->p = hpm_pattern{info.k, p->n_arcs, q->src.data(), q->dst.data(),
+                       p->vop ? q->vop.data() : nullptr, p->vop ? q->vval.data() : nullptr,
+                       p->eop ? q->eop.data() : nullptr, p->eop ? q->eval.data() : nullptr};
+    q->mode = (int)mode;
+    q->maps = mappings;
+    q->cap = mappings ? cap : 0;
+    const DevPlan plan = build_dev_plan(&q->p, info, plan_order(info, S->flags), G->n_vcols,
+                                        G->n_ecols, (int)mode);
+    q->est = estimate_scratch(G, plan);
+    q->grant = std::max(S->min_grant, std::min(q->est, S->grant_pool));
+    q->t_submit = std::chrono::steady_clock::now();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stop) fail(HPM_E_ARG, "server is shutting down");
+      q->ticket = S->next_ticket++;
+      *ticket = q->ticket;
+      S->results[q->ticket] = hpm_server::Result{};
+      S->queue.push_back(std::move(q));
+    }
+    S->cv_work.notify_one();
+    return HPM_OK;
+  });
+}
+
+int hpm_server_poll(hpm_server* S, uint64_t ticket, int32_t wait, hpm_query_result* out) {
+  return guarded([&]() -> int {
+    if (!S) fail(HPM_E_ARG, "server is NULL");
+    if (!out) fail(HPM_E_ARG, "out is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->results.find(ticket);
+    if (it == S->results.end()) fail(HPM_E_ARG, "unknown ticket");
+    if (!it->second.done) {
+      if (!wait) return HPM_PENDING;
+      S->cv_done.wait(lk, [&] {
+        auto j = S->results.find(ticket);
+        return j == S->results.end() || j->second.done;
+      });
+      it = S->results.find(ticket);
+      if (it == S->results.end()) fail(HPM_E_ARG, "ticket collected by another thread");
+    }
+    *out = it->second.r;
+    if (out->status != HPM_OK && out->status != HPM_E_TRUNCATED) t_error = it->second.error;
+    S->results.erase(it);
+    return HPM_OK;
+  });
+}
+
+int hpm_server_read_stats(hpm_server* S, hpm_server_stats* out) {
+  return guarded([&]() -> int {
+    if (!S) fail(HPM_E_ARG, "server is NULL");
+    if (!out) fail(HPM_E_ARG, "out is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->struct_size = sizeof(hpm_server_stats);
+    out->workers = S->workers;
+    out->running = S->running;
+    out->queued = (int32_t)S->queue.size();
+    out->peak_running = S->peak_running;
+    out->budget_bytes = S->budget;
+    out->grant_pool_bytes = S->grant_pool;
+    out->granted_bytes = S->in_use;
+    out->peak_granted_bytes = S->peak_in_use;
+    out->admitted = S->admitted;
+    return HPM_OK;
+  });
+}
+
+int hpm_server_destroy(hpm_server* S) {
+  return guarded([&]() -> int {
+    if (!S) return HPM_OK;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (std::thread& t : S->threads) t.join();
+    delete S;
     return HPM_OK;
   });
 }

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhpm.so")
 
 OK, E_ARG, E_GRAPH, E_PATTERN, E_NOMEM, E_TRUNCATED, E_OVERFLOW, E_DEVICE, E_UNSUPPORTED, \
     E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
@@ -27,8 +28,9 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match", "hpm_match_batch",
-           "hpm_plan_order", "hpm_last_stats", "hpm_status_string", "hpm_last_error",
-           "hpm_abi_version")
+           "hpm_server_create", "hpm_server_submit", "hpm_server_poll", "hpm_server_read_stats",
+           "hpm_server_destroy", "hpm_plan_order", "hpm_last_stats", "hpm_status_string",
+           "hpm_last_error", "hpm_abi_version")
 
 
 class HpmError(RuntimeError):
@@ -59,6 +61,26 @@ class _Stats(ctypes.Structure):
                 ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1))]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("workers", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
+
+
+class _QueryResult(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("count", ctypes.c_uint64), ("est_bytes", ctypes.c_uint64),
+                ("granted_bytes", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("workers", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64),
+                ("grant_pool_bytes", ctypes.c_uint64), ("granted_bytes", ctypes.c_uint64),
+                ("peak_granted_bytes", ctypes.c_uint64), ("admitted", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -87,6 +109,12 @@ def load() -> ctypes.CDLL:
                               ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
     lib.hpm_match_batch.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
                                     I32, P, P]
+    lib.hpm_server_create.argtypes = [ctypes.POINTER(P), P, ctypes.POINTER(_ServerOpts)]
+    lib.hpm_server_submit.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P, U64,
+                                      ctypes.POINTER(U64)]
+    lib.hpm_server_poll.argtypes = [P, U64, I32, ctypes.POINTER(_QueryResult)]
+    lib.hpm_server_read_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.hpm_server_destroy.argtypes = [P]
     lib.hpm_plan_order.argtypes = [ctypes.POINTER(_Pattern), I32, I32, ctypes.c_uint32, P]
     lib.hpm_last_stats.argtypes = [ctypes.POINTER(_Stats)]
     lib.hpm_status_string.argtypes = [ctypes.c_int]
@@ -94,7 +122,9 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-                 "hpm_match_batch", "hpm_plan_order", "hpm_last_stats"):
+                 "hpm_match_batch", "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
+                 "hpm_server_read_stats", "hpm_server_destroy", "hpm_plan_order",
+                 "hpm_last_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -192,6 +222,14 @@ def plan_order(p, n_vcols: int = 1, n_ecols: int = 1, flags: int = 0) -> list:
     return out.tolist()
 
 
+def _check_columns(g, p):
+    nv = 0 if p.vop is None else np.asarray(p.vop).shape[-1]
+    ne = 0 if p.eop is None else np.asarray(p.eop).shape[-1]
+    if (p.vop is not None and nv != g.n_vcols) or (p.eop is not None and ne != g.n_ecols):
+        raise HpmError(E_PATTERN, f"pattern has {nv} vertex / {ne} arc predicate columns, "
+                                  f"graph has {g.n_vcols} / {g.n_ecols}")
+
+
 def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None, stream=None,
           budget: int | None = None, flags: int = 0):
     """Count embeddings of pattern p in g; optionally return them.
@@ -202,11 +240,7 @@ def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None
     buffer sized to it (two calls).
     """
     lib = load()
-    nv = 0 if p.vop is None else np.asarray(p.vop).shape[-1]
-    ne = 0 if p.eop is None else np.asarray(p.eop).shape[-1]
-    if (p.vop is not None and nv != g.n_vcols) or (p.eop is not None and ne != g.n_ecols):
-        raise HpmError(E_PATTERN, f"pattern has {nv} vertex / {ne} arc predicate columns, "
-                                  f"graph has {g.n_vcols} / {g.n_ecols}")
+    _check_columns(g, p)
     s, keep = _pattern_struct(p)
     opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0))
     cnt = ctypes.c_uint64()
@@ -237,10 +271,7 @@ def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
     lib = load()
     n = len(patterns)
     for p in patterns:
-        nv = 0 if p.vop is None else np.asarray(p.vop).shape[-1]
-        ne = 0 if p.eop is None else np.asarray(p.eop).shape[-1]
-        if (p.vop is not None and nv != g.n_vcols) or (p.eop is not None and ne != g.n_ecols):
-            raise HpmError(E_PATTERN, "pattern predicate columns do not match the graph")
+        _check_columns(g, p)
     structs = (_Pattern * max(n, 1))()
     keep = []
     for i, p in enumerate(patterns):
@@ -254,6 +285,70 @@ def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
     _check(lib.hpm_match_batch(g.handle, n, structs, _ptr(md), _stream_handle(stream),
                                ctypes.byref(opts), int(workers), _ptr(counts), _ptr(status)))
     return [int(c) for c in counts[:n]], [int(x) for x in status[:n]]
+
+
+class Server:
+    """A resident graph answering queued queries (hpm_server_*).
+
+    submit() returns a ticket at once; poll(ticket) returns None while the
+    query runs (or blocks with wait=True) and then a dict with count, status,
+    queue_ms, run_ms, est_bytes and granted_bytes.  Mapping buffers passed to
+    submit are torch int32 device tensors [cap, k] kept alive until polled.
+    """
+
+    def __init__(self, g: Graph, workers: int = 0, budget: int | None = None, flags: int = 0):
+        lib = load()
+        opts = _ServerOpts(ctypes.sizeof(_ServerOpts), int(workers), int(budget or 0), flags)
+        h = ctypes.c_void_p()
+        _check(lib.hpm_server_create(ctypes.byref(h), g.handle, ctypes.byref(opts)))
+        self._h = h
+        self._g = g
+        self._bufs = {}
+
+    def submit(self, p, mode: int, mappings=None) -> int:
+        _check_columns(self._g, p)
+        s, keep = _pattern_struct(p)
+        t = ctypes.c_uint64()
+        ptr, cap = (None, 0) if mappings is None else (ctypes.c_void_p(mappings.data_ptr()),
+                                                       int(mappings.shape[0]))
+        _check(load().hpm_server_submit(self._h, ctypes.byref(s), int(mode), ptr, cap,
+                                        ctypes.byref(t)))
+        if mappings is not None:
+            self._bufs[t.value] = mappings
+        return int(t.value)
+
+    def poll(self, ticket: int, wait: bool = False):
+        r = _QueryResult()
+        st = load().hpm_server_poll(self._h, int(ticket), int(bool(wait)), ctypes.byref(r))
+        if st == PENDING:
+            return None
+        _check(st)
+        buf = self._bufs.pop(int(ticket), None)
+        out = {"status": r.status, "count": int(r.count), "queue_ms": r.queue_ms,
+               "run_ms": r.run_ms, "est_bytes": int(r.est_bytes),
+               "granted_bytes": int(r.granted_bytes)}
+        if r.status not in (OK, E_TRUNCATED):
+            out["error"] = load().hpm_last_error().decode()
+        if buf is not None and r.status == OK:
+            out["rows"] = buf[: int(r.count)]
+        return out
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(load().hpm_server_read_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in _ServerStats._fields_ if name != "struct_size"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hpm_server_destroy(self._h)
+            self._h = None
+            self._bufs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_stats() -> dict:

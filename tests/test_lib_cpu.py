@@ -148,6 +148,23 @@ def test_match_rejects_null_arguments():
                          0) == hb.E_ARG
 
 
+def test_server_entry_points_reject_null_arguments():
+    # host-side argument checks only: no server is created without a graph
+    lib = hpm.load()
+    h = ctypes.c_void_p()
+    assert lib.hpm_server_create(ctypes.byref(h), None, None) == hb.E_ARG
+    assert lib.hpm_server_create(None, None, None) == hb.E_ARG
+    p, keep = hb._pattern_struct(motif("cycle3"))
+    t = ctypes.c_uint64()
+    assert lib.hpm_server_submit(None, ctypes.byref(p), 0, None, 0, ctypes.byref(t)) == hb.E_ARG
+    r = hb._QueryResult()
+    assert lib.hpm_server_poll(None, 1, 0, ctypes.byref(r)) == hb.E_ARG
+    s = hb._ServerStats()
+    assert lib.hpm_server_read_stats(None, ctypes.byref(s)) == hb.E_ARG
+    assert lib.hpm_server_destroy(None) == hb.OK
+    assert lib.hpm_match_batch(None, 0, None, None, None, None, 0, None, None) == hb.E_ARG
+
+
 def test_motif_orders_are_valid():
     for name, (k, arcs) in MOTIFS.items():
         p = make_pattern(k, arcs, 1, 1)
