@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 1
+#define HPM_ABI_VERSION 2
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -131,9 +131,17 @@ typedef struct {
                                  (same result; for checking and measurement) */
 
 typedef struct {
-  uint32_t struct_size;      /* sizeof(hpm_match_opts)                         */
+  uint32_t struct_size;      /* sizeof(hpm_match_opts); 16 = the layout without
+                                max_matches (treated as 0)                     */
   uint32_t flags;            /* HPM_F_*                                        */
   uint64_t hbm_budget_bytes; /* scratch limit; 0 = 25% of free device memory   */
+  uint64_t max_matches;      /* first-k: stop once this many embeddings are
+                                found (0 = find all).  *count is then
+                                min(total, max_matches) and the mapping rows
+                                are that many valid embeddings, which ones
+                                unspecified.  The search runs in pieces of
+                                2^20 arcs / 2^20 candidates and stops after
+                                the piece in which the limit was reached. */
 } hpm_match_opts;
 
 /*

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <atomic>
@@ -437,6 +438,8 @@ struct Matcher {
   int64_t cap2 = 0;     // depth-2 rows per arc chunk
   int64_t chunk = 0;    // rows per frontier chunk at depth >= 3
   uint64_t budget = 0;  // scratch limit of the call
+  uint64_t limit = 0;   // stop once this many embeddings are found (0 = all)
+  bool stopped = false;
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -495,6 +498,16 @@ struct Matcher {
               "readback");
     sync();
     return W->host[slot];
+  }
+  // Total and overflow flag in one readback.
+  uint64_t read_total() {
+    static_assert(kCntOverflow == kCntTotal + 1, "adjacent counter slots");
+    hip_check(hipMemcpyAsync(W->host + kCntTotal, counters() + kCntTotal,
+                             2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+              "readback");
+    sync();
+    if (W->host[kCntOverflow]) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
+    return W->host[kCntTotal];
   }
   int64_t read_i64(const int64_t* p) {
     hip_check(hipMemcpyAsync(W->host + kCntSlots, p, sizeof(int64_t), hipMemcpyDeviceToHost, stream),
@@ -605,8 +618,8 @@ struct Matcher {
       launch(HPM_K_LAST_LEVEL, [&] {
         return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
                                   fpool, (int32_t)r, 0, work, mode, maps, counters() + kCntEmit,
-                                  maps ? cap : 0, W->partials.as<unsigned long long>(), grid,
-                                  stream);
+                                  maps ? emit_cap() : 0, W->partials.as<unsigned long long>(),
+                                  grid, stream);
       });
       launch(HPM_K_REDUCE, [&] {
         return hpm::launch_reduce_counts(W->partials.as<unsigned long long>(), grid,
@@ -616,7 +629,7 @@ struct Matcher {
       });
       return;
     }
-    for (int64_t w0 = 0; w0 < work; w0 += chunk) {
+    for (int64_t w0 = 0; w0 < work && !stopped; w0 += chunk) {
       const int64_t w1 = std::min(work, w0 + chunk);
       const int64_t n_items = w1 - w0;
       st.chunks++;
@@ -634,7 +647,16 @@ struct Matcher {
       const int64_t r1 = (int64_t)read_counter(kCntCursor);
       if (r1 > n_items) fail(HPM_E_INTERNAL, "frontier chunk overflow");
       process_depth(d + 1, out, r1);
+      check_limit();
     }
+  }
+
+  // Rows the last level may write: the caller's capacity, at most the limit.
+  uint64_t emit_cap() const { return limit ? std::min(cap, limit) : cap; }
+
+  // First-k: stop once the running total reaches the limit.
+  void check_limit() {
+    if (limit && !stopped && read_total() >= limit) stopped = true;
   }
 
   void run() {
@@ -651,7 +673,7 @@ struct Matcher {
         zero_counter(kCntCursor);
         launch(HPM_K_EDGE_SCAN, [&] {
           return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 2, maps,
-                                       counters() + kCntCursor, cap,
+                                       counters() + kCntCursor, emit_cap(),
                                        W->partials.as<unsigned long long>(), grid, stream);
         });
         c = read_counter(kCntCursor);
@@ -669,16 +691,16 @@ struct Matcher {
                                            reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
                                            stream);
         });
-        c = read_counter(kCntTotal);
-        if (read_counter(kCntOverflow)) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
+        c = read_total();
       }
       st.survivors = c;
       st.rows[2] = c;
-      st.count = c;
+      st.count = limit ? std::min(c, limit) : c;
       return;
     }
-    for (int64_t e0 = 0; e0 < m; e0 += cap2) {
+    for (int64_t e0 = 0; e0 < m && !stopped; e0 += cap2) {
       const int64_t e1 = std::min<int64_t>(m, e0 + cap2);
+      st.arcs_scanned = (uint64_t)e1;
       const int grid = (int)hpm::edge_scan_blocks(e1 - e0);
       W->blkcount.ensure((size_t)(grid + 1) * sizeof(int64_t), stream);
       W->blkprefix.ensure((size_t)(grid / hpm::kPivotTile + 2) * sizeof(int64_t), stream);
@@ -703,13 +725,18 @@ struct Matcher {
                                         (int32_t)e1, W->rows2d.as<int32_t>(), s2, stream);
       });
       process_depth(2, W->rows2d.as<int32_t>(), s2);
+      check_limit();
     }
-    st.count = read_counter(kCntTotal);
-    if (read_counter(kCntOverflow)) fail(HPM_E_OVERFLOW, "embedding count exceeds 2^64-1");
+    st.count = read_total();
+    if (limit) st.count = std::min(st.count, limit);
   }
 };
 
 constexpr uint64_t kMinChunkRows = hpm::kExpandTile;
+// Piece sizes of a first-k search (arcs per scan chunk, work items per
+// frontier chunk).
+constexpr int64_t kFirstKArcs = int64_t(1) << 20;
+constexpr int64_t kFirstKRows = int64_t(1) << 20;
 
 }  // namespace
 
@@ -890,7 +917,7 @@ inline uint64_t row_bytes(int32_t d) { return 4 * (uint64_t)d + 17; }
 // Workspace: NULL takes one from the graph's pool (returned on exit).
 int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, uint32_t flags,
               uint64_t budget, uint64_t* count, int32_t* mappings, uint64_t cap,
-              hpm_match_stats* stats, Workspace* own = nullptr) {
+              hpm_match_stats* stats, Workspace* own = nullptr, uint64_t limit = 0) {
     const auto t0 = std::chrono::steady_clock::now();
     if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
     PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
@@ -943,6 +970,13 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       }
     }
 
+    if (limit) {
+      // first-k: work in small pieces so the search can stop soon after the
+      // limit is reached
+      cap2 = std::min<int64_t>(cap2, kFirstKArcs);
+      if (chunk) chunk = std::min<int64_t>(chunk, kFirstKRows);
+    }
+
     Workspace* W = own;
     if (!W) {
       std::lock_guard<std::mutex> lk(G->mu);
@@ -975,6 +1009,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     M.cap2 = cap2;
     M.chunk = chunk;
     M.budget = budget;
+    M.limit = limit;
     W->plan.ensure(sizeof(DevPlan), stream);
     W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);
@@ -990,8 +1025,6 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
               "plan upload");
     hip_check(hipMemsetAsync(W->counters.p, 0, 8 * sizeof(unsigned long long), stream), "memset");
     M.run();
-    uint64_t emitted = 0;
-    if (mappings && k >= 3) emitted = M.read_counter(kCntEmit);
     M.sync();
     M.st.struct_size = sizeof(hpm_match_stats);
     M.st.scratch_bytes = W->held();
@@ -999,7 +1032,6 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *count = M.st.count;
     if (stats) *stats = M.st;
-    (void)emitted;
     if (mappings && M.st.count > cap) {
       t_error = "count " + std::to_string(M.st.count) + " exceeds cap " + std::to_string(cap);
       return HPM_E_TRUNCATED;
@@ -1193,6 +1225,21 @@ struct hpm_server {
   }
 };
 
+namespace {
+
+// Options of hpm_match / hpm_match_batch.  Callers built against the first
+// layout (no max_matches) pass the smaller struct_size.
+void read_opts(const hpm_match_opts* opts, uint32_t* flags, uint64_t* budget, uint64_t* limit) {
+  if (!opts) return;
+  constexpr uint32_t kV1 = offsetof(hpm_match_opts, max_matches);
+  if (opts->struct_size < kV1) fail(HPM_E_ARG, "opts.struct_size too small");
+  *flags = opts->flags;
+  *budget = opts->hbm_budget_bytes;
+  if (opts->struct_size >= sizeof(hpm_match_opts)) *limit = opts->max_matches;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
@@ -1201,14 +1248,10 @@ int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* st
     if (!gc) fail(HPM_E_ARG, "graph is NULL");
     if (!count) fail(HPM_E_ARG, "count is NULL");
     uint32_t flags = 0;
-    uint64_t budget = 0;
-    if (opts) {
-      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
-      flags = opts->flags;
-      budget = opts->hbm_budget_bytes;
-    }
+    uint64_t budget = 0, limit = 0;
+    read_opts(opts, &flags, &budget, &limit);
     return match_one(const_cast<hpm_graph*>(gc), p, (int)mode, static_cast<hipStream_t>(stream),
-                     flags, budget, count, mappings, cap, &t_stats);
+                     flags, budget, count, mappings, cap, &t_stats, nullptr, limit);
   });
 }
 
@@ -1223,12 +1266,9 @@ int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
     if (workers == 0) workers = 4;
     workers = std::min<int32_t>(workers, std::max<int32_t>(n, 1));
     uint32_t flags = 0;
-    uint64_t budget = 0;
-    if (opts) {
-      if (opts->struct_size < sizeof(hpm_match_opts)) fail(HPM_E_ARG, "opts.struct_size too small");
-      flags = opts->flags & ~(uint32_t)HPM_F_TIMING;
-      budget = opts->hbm_budget_bytes;
-    }
+    uint64_t budget = 0, limit = 0;
+    read_opts(opts, &flags, &budget, &limit);
+    flags &= ~(uint32_t)HPM_F_TIMING;
     hpm_graph* G = const_cast<hpm_graph*>(gc);
     hip_check(hipSetDevice(G->device), "hipSetDevice");
     if (budget == 0) {
@@ -1249,7 +1289,7 @@ int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
         try {
           if (!s) fail(HPM_E_DEVICE, "hipStreamCreateWithFlags failed");
           status[i] = match_one(G, &patterns[i], modes[i], s, flags, share, &counts[i], nullptr, 0,
-                                nullptr);
+                                nullptr, nullptr, limit);
         } catch (const Failure& f) {
           status[i] = f.status;
           errors[i] = f.msg;

@@ -48,7 +48,7 @@ class _Pattern(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("max_matches", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -231,18 +231,19 @@ def _check_columns(g, p):
 
 
 def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None, stream=None,
-          budget: int | None = None, flags: int = 0):
+          budget: int | None = None, flags: int = 0, max_matches: int = 0):
     """Count embeddings of pattern p in g; optionally return them.
 
     Returns (count, rows) where rows is None or an int32 torch tensor [count, k]
     on the current device (original pattern-vertex order, unspecified row
     order).  With mappings=True and cap=None the count is taken first and the
-    buffer sized to it (two calls).
+    buffer sized to it (two calls).  max_matches > 0 stops the search once that
+    many embeddings are found (first-k): the count is then at most max_matches.
     """
     lib = load()
     _check_columns(g, p)
     s, keep = _pattern_struct(p)
-    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0))
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), int(max_matches))
     cnt = ctypes.c_uint64()
     sh = _stream_handle(stream)
     if not mappings:
@@ -262,7 +263,7 @@ def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None
 
 
 def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
-                budget: int | None = None, flags: int = 0):
+                budget: int | None = None, flags: int = 0, max_matches: int = 0):
     """Counts of many patterns on one graph (hpm_match_batch).
 
     Returns (counts, statuses) as lists; raises HpmError if any pattern failed
@@ -281,7 +282,7 @@ def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
     md = np.ascontiguousarray(modes, dtype=np.int32)
     counts = np.zeros(max(n, 1), dtype=np.uint64)
     status = np.zeros(max(n, 1), dtype=np.int32)
-    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0))
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), int(max_matches))
     _check(lib.hpm_match_batch(g.handle, n, structs, _ptr(md), _stream_handle(stream),
                                ctypes.byref(opts), int(workers), _ptr(counts), _ptr(status)))
     return [int(c) for c in counts[:n]], [int(x) for x in status[:n]]

@@ -340,3 +340,37 @@ def test_batch_equals_single_and_oracle():
     bad = make_pattern(4, [(0, 1), (2, 3)], 1, 1)
     with pytest.raises(hpm.HpmError):
         hpm.match_batch(dg, pats[:3] + [bad], modes[:3] + [ISO], workers=2)
+
+
+def test_first_k_stops_early_with_valid_rows():
+    # max_matches: the count is min(total, limit) and every returned row is an
+    # embedding from the oracle's set; a small limit stops the arc scan early.
+    g = rmat(12, 1 << 15, seed=41)
+    dg = hpm.Graph.from_host(g)
+    p = motif("star3_back", vlabels=[0, 0, 0, 0])
+    for mode in (ISO, MONO):
+        want = oracle.match(g, p, mode, threads=8)
+        total = want.count
+        assert total > 1000
+        full = {tuple(r) for r in want.rows.tolist()}
+        for limit in (1, 7, 1000, total - 1, total, total + 5):
+            c, _ = hpm.match(dg, p, mode, max_matches=limit)
+            assert c == min(limit, total)
+            c2, t = hpm.match(dg, p, mode, mappings=True, cap=min(limit, total),
+                              max_matches=limit)
+            assert c2 == min(limit, total)
+            rows = t.cpu().numpy()
+            assert rows.shape == (c2, p.k)
+            got = {tuple(r) for r in rows.tolist()}
+            assert len(got) == c2 and got <= full
+    say(f"first-k on scale 12: total {total}")
+    big = rmat(17, 1 << 21, seed=42)
+    dbig = hpm.Graph.from_host(big)
+    c, _ = hpm.match(dbig, motif("cycle3"), MONO, max_matches=1)
+    st = hpm.last_stats()
+    assert c == 1 and st["arcs_scanned"] < big.m
+    call, _ = hpm.match(dbig, motif("cycle3"), MONO)
+    assert hpm.last_stats()["arcs_scanned"] == big.m and call > 1
+    counts, _ = hpm.match_batch(dbig, [motif("cycle3")] * 3, [MONO, ISO, MONO], workers=2,
+                                max_matches=5)
+    assert counts == [min(5, hpm.match(dbig, motif("cycle3"), m)[0]) for m in (MONO, ISO, MONO)]

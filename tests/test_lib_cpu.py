@@ -28,7 +28,34 @@ def test_library_exports_every_declared_function():
     assert set(declared) == set(hb.EXPORTS)
     for name in declared:
         assert hasattr(lib, name), name
-    assert hpm.abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "hpm.h")).read()
+    assert hpm.abi_version() == int(re.search(r"#define HPM_ABI_VERSION (\d+)", hdr).group(1))
+
+
+def test_struct_mirrors_match_the_header(tmp_path):
+    # the ctypes mirrors have the sizes and field offsets a C compiler gives
+    # the header's structs
+    mirrors = {"hpm_match_opts": hb._Opts, "hpm_server_opts": hb._ServerOpts,
+               "hpm_query_result": hb._QueryResult, "hpm_server_stats": hb._ServerStats,
+               "hpm_match_stats": hb._Stats, "hpm_pattern": hb._Pattern}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hpm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, what, val = line.split()
+        py = mirrors[cname]
+        got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), line
 
 
 def test_status_strings():
