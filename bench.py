@@ -54,6 +54,19 @@ def workload(name):
         runs = [(configs.c1_pattern(), ISO), (configs.c1u_pattern(), ISO),
                 (configs.c1u_pattern(), MONO)]
         desc = "Erdos-Renyi 1000 vertices / 5000 arcs, labelled and unlabelled 3-cycle"
+    elif name == "batch256":
+        g = configs.c2_graph()
+        runs = configs.c4_patterns()
+        desc = ("R-MAT scale 20 graph as rmat20; 256 random patterns of 3-8 vertices (spanning "
+                "tree plus pairs up to density 0.6, Zipf vertex labels, U{0..3} arc labels, iso "
+                "or mono), each within a fixed oracle search bound on this graph; one batched call")
+    elif name == "serve":
+        g = configs.c3_graph()
+        runs = [(p, m) for p, m, _, _ in configs.c5_pool()]
+        desc = ("connectome-shaped graph as chunglu, resident; a pool of random 3-8 vertex "
+                "queries (labels U{0..7}, arc weight >= 10, iso or mono), each within a fixed "
+                "oracle search bound; Poisson arrivals at fixed rates, served by hpm_server vs "
+                "one hpm_match at a time in arrival order")
     elif name == "chunglu":
         g = configs.c3_graph()
         runs = [(p, MONO) for p in configs.c3_patterns()]
@@ -76,6 +89,29 @@ def kernel_bytes(stats_list, g, runs):
         if k >= 3:
             out["last_level"] += B_CAND * st["work"][k - 1]
     return out
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2507_04130_amd", "csrc", "hpm_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
+    each scaled by the same counter on a 1 GiB device copy), or None when the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith(f"kernel={kernel} "):
+            fields = dict(kv.split("=", 1) for kv in line.split())
+    if not fields or fields.get("source_sha256") != kernel_source_sha():
+        return None
+    return int(float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"]))
 
 
 def cpu_baseline(g, runs, seconds_target):
@@ -109,12 +145,78 @@ def cpu_baseline(g, runs, seconds_target):
                       f"{found} matches in {secs:.1f} s"}
 
 
+def serve_trace(hpm, dg, runs, expected, qps, n, kind, workers, budget, stream):
+    """Replay one seeded Poisson trace; latency is result time minus scheduled
+    arrival.  kind "served": every query is submitted to an hpm_server at its
+    arrival time; "one_at_a_time": one hpm_match after another in arrival
+    order, each started at its arrival or when the previous one returns."""
+    import numpy as np
+    from synth import configs
+    arrivals, idx = configs.c5_trace(qps, n, len(runs))
+    warm = n // 10
+    lat = np.zeros(n)
+    got = [None] * n
+    if kind == "served":
+        srv = hpm.Server(dg, workers=workers, budget=budget)
+        tickets, late = [], np.zeros(n)
+        t0 = time.perf_counter()
+        for i in range(n):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            late[i] = time.perf_counter() - t0 - arrivals[i]
+            p, mode = runs[idx[i]]
+            tickets.append(srv.submit(p, mode))
+        for i, t in enumerate(tickets):
+            r = srv.poll(t, wait=True)
+            assert r["status"] == 0, r
+            got[i] = r["count"]
+            lat[i] = late[i] + (r["queue_ms"] + r["run_ms"]) / 1000.0
+        st = srv.stats()
+        srv.close()
+        done = arrivals + lat
+    else:
+        st = None
+        done = np.zeros(n)
+        t0 = time.perf_counter()
+        for i in range(n):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            p, mode = runs[idx[i]]
+            got[i], _ = hpm.match(dg, p, mode, stream=stream)
+            done[i] = time.perf_counter() - t0
+        lat = done - arrivals
+    bad = [i for i in range(n) if got[i] != expected[idx[i]]]
+    assert not bad, f"{kind} counts differ from the oracle's at {bad[:8]}"
+    span = float(done[warm:].max() - arrivals[warm])
+    matches = int(sum(expected[idx[i]] for i in range(warm, n)))
+    out = {"p50_ms": 1000.0 * float(np.percentile(lat[warm:], 50)),
+           "p99_ms": 1000.0 * float(np.percentile(lat[warm:], 99)),
+           "mean_ms": 1000.0 * float(lat[warm:].mean()),
+           "queries_per_sec": (n - warm) / span, "matches_per_sec": matches / span,
+           "matches": matches, "span_s": span, "measured": n - warm}
+    if st:
+        out["peak_running"] = st["peak_running"]
+        out["peak_granted_gib"] = round(st["peak_granted_bytes"] / 2**30, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20", choices=["rmat20", "er1k", "chunglu"])
+    ap.add_argument("--workload", default="rmat20",
+                    choices=["rmat20", "er1k", "chunglu", "batch256", "serve"])
+    ap.add_argument("--batch-workers", type=int, default=4,
+                    help="host threads / streams of the batched call (batch256)")
+    ap.add_argument("--qps", default="20,100,500",
+                    help="arrival rates of the serve workload (comma separated)")
+    ap.add_argument("--serve-queries", type=int, default=300,
+                    help="queries per arrival rate (serve); the first tenth are warm-up")
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -155,22 +257,110 @@ def main():
             stats.append(hpm.last_stats())
         return counts, stats
 
-    for i in range(args.warmup):
-        counts, _ = step(False)
-        log(f"warmup {i}: counts={counts}")
-    torch.cuda.synchronize()
-    all_stats = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        counts, stats = step(True)
-        all_stats.extend(stats)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    log(f"timed {args.steps} steps in {elapsed:.3f}s")
+    batch = args.workload == "batch256"
+    serve = args.workload == "serve"
+    pats = [p for p, _ in runs]
+    modes = [m for _, m in runs]
+    extra = {}
+    if batch:
+        # one batched call per step; per-kernel times come from one sequential
+        # step with HIP events, which is also the one-at-a-time comparison
+        from synth import configs
+        expected = configs.c4_expected_counts(len(runs))
+        seq_counts, all_stats = [], []
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter()
+        for i, (p, mode) in enumerate(runs):
+            c, _ = hpm.match(dg, p, mode, stream=stream, flags=hpm.F_TIMING)
+            seq_counts.append(c)
+            all_stats.append(hpm.last_stats())
+            if i % 32 == 31:
+                log(f"sequential: {i + 1} queries, {time.perf_counter() - t_seq:.3f}s")
+        seq_s = time.perf_counter() - t_seq
+        bad = [i for i, (a, b) in enumerate(zip(seq_counts, expected)) if a != b]
+        assert not bad, f"counts differ from the oracle's for patterns {bad[:8]}"
+        log(f"sequential step {seq_s:.3f}s; all {len(runs)} counts equal the oracle's")
+        for i in range(args.warmup):
+            hpm.match_batch(dg, pats, modes, workers=args.batch_workers, stream=stream)
+            torch.cuda.synchronize()
+            log(f"batched warmup {i} done")
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            counts, status = hpm.match_batch(dg, pats, modes, workers=args.batch_workers,
+                                             stream=stream)
+            log(f"batched step {i}: {time.perf_counter() - t_start:.3f}s")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        assert counts == expected, "batched counts differ from the oracle's"
+        extra = {"batch_workers": args.batch_workers,
+                 "queries_per_sec": len(runs) * args.steps / elapsed,
+                 "sequential_queries_per_sec": len(runs) / seq_s,
+                 "sequential_ms_per_step": 1000.0 * seq_s,
+                 "batch_speedup": (seq_s * args.steps) / elapsed}
+        log(f"batched {args.steps} steps in {elapsed:.3f}s; sequential step {seq_s:.3f}s")
+        timed_steps = 1
+    elif serve:
+        from synth import configs
+        pool = configs.c5_pool()
+        expected = [c for _, _, c, _ in pool]
+        # one sequential pass with HIP events: per-kernel times, and every
+        # count checked against the oracle's
+        seq_counts, all_stats = [], []
+        t_seq = time.perf_counter()
+        for i, (p, mode) in enumerate(runs):
+            c, _ = hpm.match(dg, p, mode, stream=stream, flags=hpm.F_TIMING)
+            seq_counts.append(c)
+            all_stats.append(hpm.last_stats())
+            if i % 32 == 31:
+                log(f"pool pass: {i + 1} queries, {time.perf_counter() - t_seq:.3f}s")
+        seq_s = time.perf_counter() - t_seq
+        bad = [i for i, (a, b) in enumerate(zip(seq_counts, expected)) if a != b]
+        assert not bad, f"counts differ from the oracle's for queries {bad[:8]}"
+        log(f"pool pass {seq_s:.3f}s; all {len(runs)} counts equal the oracle's")
+        rates = [float(x) for x in args.qps.split(",") if x]
+        sweep = []
+        for qps in rates:
+            rec = {"qps": qps}
+            for kind in ("served", "one_at_a_time"):
+                r = serve_trace(hpm, dg, runs, expected, qps, args.serve_queries, kind,
+                                args.serve_workers, int(args.serve_budget_gib * 2**30), stream)
+                rec[kind] = r
+                log(f"qps {qps} {kind}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms, "
+                    f"{r['queries_per_sec']:.1f} q/s, {r['matches_per_sec']:.3e} matches/s")
+            sweep.append(rec)
+        top = sweep[-1]["served"]
+        counts = seq_counts
+        elapsed = top["span_s"]
+        extra = {"serve_workers": args.serve_workers,
+                 "serve_budget_gib": args.serve_budget_gib,
+                 "pool_size": len(runs), "queries_per_rate": args.serve_queries,
+                 "sweep": sweep,
+                 "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+                 "queries_per_sec": top["queries_per_sec"]}
+        timed_steps = 1
+        args.steps, args.warmup = 1, 0     # one trace replay at the highest rate
+    else:
+        for i in range(args.warmup):
+            counts, _ = step(False)
+            log(f"warmup {i}: counts={counts}")
+        torch.cuda.synchronize()
+        all_stats = []
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            counts, stats = step(True)
+            all_stats.extend(stats)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        log(f"timed {args.steps} steps in {elapsed:.3f}s")
+        timed_steps = args.steps
 
     matches_per_step = sum(counts)
     ms_per_step = 1000.0 * elapsed / args.steps
     value = matches_per_step * args.steps / elapsed
+    if serve:
+        matches_per_step = extra["sweep"][-1]["served"]["matches"]
+        ms_per_step = 1000.0 * elapsed
+        value = extra["sweep"][-1]["served"]["matches_per_sec"]
 
     fam_ms, fam_launch = {}, {}
     for st in all_stats:
@@ -178,17 +368,18 @@ def main():
             fam_ms[kname] = fam_ms.get(kname, 0.0) + ms
             fam_launch[kname] = fam_launch.get(kname, 0) + st["kernel_launches"][kname]
     scan_ms = fam_ms.get("edge_scan", 0.0)
-    cand_per_s = g.m * len(runs) * args.steps / (scan_ms / 1000.0) if scan_ms > 0 else None
+    cand_per_s = g.m * len(runs) * timed_steps / (scan_ms / 1000.0) if scan_ms > 0 else None
     surv = sum(st["survivors"] for st in all_stats)
 
-    bytes_by = kernel_bytes(all_stats, g, runs * args.steps)
+    bytes_by = kernel_bytes(all_stats, g, runs * timed_steps)
     costed = {k: v for k, v in fam_ms.items() if k in bytes_by and v > 0}
     dom = max(costed, key=costed.get)
     launches = fam_launch[dom]
     avg_ms = fam_ms[dom] / launches
     achieved = bytes_by[dom] / (fam_ms[dom] / 1000.0) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, dom),
                 "kernel": dom, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(bytes_by[dom] / launches)}
     scan_gbs = bytes_by["edge_scan"] / (scan_ms / 1000.0) / 1e9 if scan_ms > 0 else None
@@ -199,14 +390,15 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n": g.n, "m": g.m,
-                   "queries": [f"{p.name}/{'iso' if mode == 0 else 'mono'}" for p, mode in runs],
+                   "queries": ([f"{p.name}/{'iso' if mode == 0 else 'mono'}" for p, mode in runs]
+                               if len(runs) <= 16 else f"{len(runs)} patterns"),
                    "matches_per_step": matches_per_step},
         "validated_edge_candidates_per_sec": cand_per_s,
         "survivors_per_sec": surv / (scan_ms / 1000.0) if scan_ms > 0 else None,
         "edge_scan_gbs": scan_gbs,
-        "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in fam_ms.items()},
-        "counts": counts,
-        "per_query": [{"query": f"{p.name}/{'iso' if mode == 0 else 'mono'}", "count": st["count"],
+        "kernel_ms_per_step": {k: round(v / timed_steps, 4) for k, v in fam_ms.items()},
+        "counts": counts if len(runs) <= 16 else None,
+        "per_query": [] if len(runs) > 16 else [{"query": f"{p.name}/{'iso' if mode == 0 else 'mono'}", "count": st["count"],
                        "survivors": st["survivors"], "rows": st["rows"][2:p.k],
                        "work": st["work"][2:p.k], "raw_work": st["raw_work"][2:p.k],
                        "filtered_lists": st["filtered_lists"],
@@ -214,6 +406,7 @@ def main():
                       for st, (p, mode) in zip(all_stats[-len(runs):], runs)],
         "roofline": roofline,
     }
+    out.update(extra)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, runs, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -100,7 +100,10 @@ def c3_patterns():
     return out
 
 
-def c4_patterns(count: int = 256):
+def c4_draws(count: int):
+    """The first `count` random pattern draws of the batched workload (pattern
+    seed): sizes U{3..8}, spanning tree plus pairs up to density U[tree, 0.6],
+    Zipf vertex labels, U{0..3} arc labels, mode iso or mono with p = 1/2."""
     rng = np.random.default_rng(PATTERN_SEEDS["c4"])
     out = []
     for i in range(count):
@@ -108,3 +111,71 @@ def c4_patterns(count: int = 256):
         mode = ISO if rng.random() < 0.5 else MONO
         out.append((p, mode))
     return out
+
+
+def _c4_screened():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests",
+                        "golden", "batch_patterns_screened.json")
+    with open(path) as f:
+        return json.load(f)["accepted"]
+
+
+def c4_patterns(count: int = 256):
+    """The batched workload: the draws accepted by the oracle screening stored
+    in tests/golden/batch_patterns_screened.json (the search on the full graph
+    stays within a fixed bound of partial mappings), in draw order."""
+    acc = [a["draw"] for a in _c4_screened()][:count]
+    draws = c4_draws(max(acc) + 1)
+    return [draws[i] for i in acc]
+
+
+def c4_expected_counts(count: int = 256):
+    """The oracle's embedding counts of c4_patterns(count) on the full graph."""
+    return [a["count"] for a in _c4_screened()][:count]
+
+
+def c5_draws(count: int):
+    """Random query draws of the served workload (pattern seed): shapes as the
+    batched workload's, vertex labels U{0..7} on every vertex, every arc
+    weight >= the connectome threshold, iso or mono with p = 1/2."""
+    rng = np.random.default_rng(PATTERN_SEEDS["c5"])
+    out = []
+    for i in range(count):
+        p = random_pattern(rng, vlabels=("uniform", 8), eop=GE, eval_const=C3_THRESHOLD,
+                           name=f"c5_{i}")
+        mode = ISO if rng.random() < 0.5 else MONO
+        out.append((p, mode))
+    return out
+
+
+def _c5_screened():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests",
+                        "golden", "serve_patterns_screened.json")
+    with open(path) as f:
+        return json.load(f)["accepted"]
+
+
+def c5_pool():
+    """The served workload's query pool: draws accepted by the oracle screening
+    in tests/golden/serve_patterns_screened.json, with their oracle counts and
+    fingerprints on the full connectome graph: [(pattern, mode, count, fp)]."""
+    acc = _c5_screened()
+    draws = c5_draws(max(a["draw"] for a in acc) + 1)
+    return [(draws[a["draw"]][0], draws[a["draw"]][1], a["count"], tuple(a["fingerprint"]))
+            for a in acc]
+
+
+ARRIVAL_SEED = 305
+
+
+def c5_trace(qps: float, n: int, pool_size: int, seed: int = ARRIVAL_SEED):
+    """Poisson arrivals: (arrival time in s from the first, pool index) for n
+    queries at rate qps, seeded per rate."""
+    rng = np.random.default_rng([seed, int(round(qps * 1000))])
+    gaps = rng.exponential(1.0 / qps, size=n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps), rng.integers(0, pool_size, size=n)
