@@ -145,7 +145,7 @@ def cpu_baseline(g, runs, seconds_target):
                       f"{found} matches in {secs:.1f} s"}
 
 
-def serve_trace(hpm, dg, runs, expected, qps, n, kind, workers, budget, stream):
+def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
     """Replay one seeded Poisson trace; latency is result time minus scheduled
     arrival.  kind "served": every query is submitted to an hpm_server at its
     arrival time; "one_at_a_time": one hpm_match after another in arrival
@@ -157,7 +157,7 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, workers, budget, stream):
     lat = np.zeros(n)
     got = [None] * n
     if kind == "served":
-        srv = hpm.Server(dg, workers=workers, budget=budget)
+        admitted0 = srv.stats()["admitted"]
         tickets, late = [], np.zeros(n)
         t0 = time.perf_counter()
         for i in range(n):
@@ -173,7 +173,7 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, workers, budget, stream):
             got[i] = r["count"]
             lat[i] = late[i] + (r["queue_ms"] + r["run_ms"]) / 1000.0
         st = srv.stats()
-        srv.close()
+        assert st["admitted"] - admitted0 == n
         done = arrivals + lat
     else:
         st = None
@@ -197,8 +197,8 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, workers, budget, stream):
            "queries_per_sec": (n - warm) / span, "matches_per_sec": matches / span,
            "matches": matches, "span_s": span, "measured": n - warm}
     if st:
-        out["peak_running"] = st["peak_running"]
-        out["peak_granted_gib"] = round(st["peak_granted_bytes"] / 2**30, 3)
+        out["peak_running_so_far"] = st["peak_running"]
+        out["peak_granted_gib_so_far"] = round(st["peak_granted_bytes"] / 2**30, 3)
     return out
 
 
@@ -211,9 +211,9 @@ def main():
                     choices=["rmat20", "er1k", "chunglu", "batch256", "serve"])
     ap.add_argument("--batch-workers", type=int, default=4,
                     help="host threads / streams of the batched call (batch256)")
-    ap.add_argument("--qps", default="20,100,500",
+    ap.add_argument("--qps", default="100,500,1000,2000",
                     help="arrival rates of the serve workload (comma separated)")
-    ap.add_argument("--serve-queries", type=int, default=300,
+    ap.add_argument("--serve-queries", type=int, default=400,
                     help="queries per arrival rate (serve); the first tenth are warm-up")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
@@ -318,16 +318,27 @@ def main():
         assert not bad, f"counts differ from the oracle's for queries {bad[:8]}"
         log(f"pool pass {seq_s:.3f}s; all {len(runs)} counts equal the oracle's")
         rates = [float(x) for x in args.qps.split(",") if x]
+        # one server for the whole sweep, warmed by two passes over the pool
+        # (every worker's scratch grows to its working size before timing)
+        srv = hpm.Server(dg, workers=args.serve_workers,
+                         budget=int(args.serve_budget_gib * 2**30))
+        t_w = time.perf_counter()
+        for rep in range(2):
+            tk = [srv.submit(p, mode) for p, mode in runs]
+            got = [srv.poll(t, wait=True)["count"] for t in tk]
+            assert got == expected, "served counts differ from the oracle's"
+        log(f"server warm-up: 2 x {len(runs)} queries in {time.perf_counter() - t_w:.3f}s")
         sweep = []
         for qps in rates:
             rec = {"qps": qps}
             for kind in ("served", "one_at_a_time"):
-                r = serve_trace(hpm, dg, runs, expected, qps, args.serve_queries, kind,
-                                args.serve_workers, int(args.serve_budget_gib * 2**30), stream)
+                r = serve_trace(hpm, dg, runs, expected, qps, args.serve_queries, kind, srv,
+                                stream)
                 rec[kind] = r
                 log(f"qps {qps} {kind}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms, "
                     f"{r['queries_per_sec']:.1f} q/s, {r['matches_per_sec']:.3e} matches/s")
             sweep.append(rec)
+        srv.close()
         top = sweep[-1]["served"]
         counts = seq_counts
         elapsed = top["span_s"]
