@@ -24,6 +24,8 @@ constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront sta
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
 constexpr int kFilterMinLen = 32;     // pivot lists at least this long are pre-filtered
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
+constexpr int kAlignMin = 512;        // rows with this many candidates get tiles of their own
+constexpr int kMarkEntries = 4 * kExpandTile;  // longest list window marked into a tile
 
 // Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.
 struct DevGraph {
@@ -126,12 +128,21 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 // out_mode: 0 write depth d+1 rows; 1 count only; 2 count and write final rows.
 // fpool: pre-filtered candidate lists (rows whose pivot code has bit 1 set).
 // abits: the validator bitmap of position d.
+// toff NULL: packed tiles over work items [w_begin, w_end) of the prefix sums
+// off.  toff non-NULL: w_end tiles of long rows (toff = their tile prefix sums
+// from launch_split_rows, off = the full length prefix sums).
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
-                         int out_mode, int32_t* out, unsigned long long* cursor,
-                         unsigned long long out_cap, unsigned long long* partials, int grid,
-                         hipStream_t stream);
+                         const int64_t* toff, int out_mode, int32_t* out,
+                         unsigned long long* cursor, unsigned long long out_cap,
+                         unsigned long long* partials, int grid, hipStream_t stream);
+// Split rows by list length (prefix sums off[0..r]): soff[0..r] = prefix sums
+// of the lengths of rows shorter than kAlignMin (long rows count 0), toff[0..r]
+// = prefix sums of the tile counts of long rows; sbsum/tbsum as for
+// launch_scan_lengths.
+hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64_t* toff,
+                             int64_t* sbsum, int64_t* tbsum, hipStream_t stream);
 // Pivot-list filter.  off: the rows' exclusive length prefix sums.  keys[H]
 // must hold ~0 (empty) on entry, H a power of two above the number of rows
 // with a list of >= min_len entries.  Inserts their keys, then numbers the

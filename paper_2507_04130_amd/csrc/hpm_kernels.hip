@@ -653,23 +653,31 @@ __device__ __forceinline__ bool tile_bitmap(int32_t cmin, int32_t cmax) {
   return (((int64_t)cmax - cmin) >> 5) < kTilePool;
 }
 
-template <int OUT>
+template <int OUT, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_expand(
     DevGraph g, const DevPlan* __restrict__ P, const uint32_t* __restrict__ abits, int32_t d,
     const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
     const int2* __restrict__ piv, const int32_t* __restrict__ fpool, int32_t r, int64_t w_begin,
-    int64_t w_end, int32_t* __restrict__ out, unsigned long long* __restrict__ cursor,
-    unsigned long long out_cap, unsigned long long* __restrict__ partials) {
-  // Work item w in [w_begin, w_end) is candidate j = w - off[i] of the row i
-  // with off[i] <= w < off[i+1]: entry j of that row's pivot list.  A tile of
-  // kExpandTile consecutive items covers rows [r_lo, r_hi]; their prefix sums,
-  // pivots and (if small) the rows themselves are staged in LDS.
+    int64_t w_end, const int64_t* __restrict__ toff, int32_t* __restrict__ out,
+    unsigned long long* __restrict__ cursor, unsigned long long out_cap,
+    unsigned long long* __restrict__ partials) {
+  // Packed tiles (LONG false): work item w in [w_begin, w_end) is candidate
+  // j = w - off[i] of the row i with off[i] <= w < off[i+1] (entry j of that
+  // row's pivot list); a tile of kExpandTile consecutive items covers rows
+  // [r_lo, r_hi], whose prefix sums, pivots and (if small) the rows themselves
+  // are staged in LDS.  Rows of zero length are never selected.
+  // Row tiles (LONG true): w_end tiles; tile t is segment s = t - toff[i] of the
+  // row i with toff[i] <= t < toff[i+1], i.e. entries [s, s+1) * kExpandTile
+  // (cut at the row's length off[i+1] - off[i]) of that row's list.
   //
   // Membership tests (is f(q) -> c an arc?) go three ways:
-  //  * tile inside one row (long pivot lists): the tile's candidates are the
-  //    sorted run [cmin, cmax] of one list, so every checked list is cut to
-  //    that window once per tile; the window becomes an LDS bitmap over
-  //    [cmin, cmax] (or, for a wide id range, is staged and binary-searched);
+  //  * tile inside one row (every row tile; packed tiles of long lists): the
+  //    tile's candidates are the sorted run [cmin, cmax] of one list, so every
+  //    checked list is cut to that window once per tile; the window becomes an
+  //    LDS bitmap over [cmin, cmax] when that id range is narrow, else each
+  //    entry of a short enough window is looked up among the tile's staged
+  //    candidates and marks its position, else candidates binary-search the
+  //    cut window;
   //  * wavefront inside one row: checked lists of at most kWaveList entries
   //    are staged in the wavefront's LDS slice;
   //  * otherwise each lane binary-searches the list of the mapped vertex.
@@ -677,10 +685,14 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   __shared__ int2 s_piv[kExpandTile];
   __shared__ int32_t s_rows[kLdsRowInts];
   __shared__ int32_t s_pool[kTilePool];
-  __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
+  __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons];
   __shared__ int32_t s_misc[5];
   __shared__ unsigned long long s_scan[kWaves + 1];
   __shared__ unsigned long long s_base;
+  // Single-row tiles leave most of s_off and s_piv unused: the tile's
+  // candidates (in order) and their hit mask live there.
+  int32_t* s_cand = reinterpret_cast<int32_t*>(s_off + 2);
+  uint32_t* s_mark = reinterpret_cast<uint32_t*>(s_piv + 1);
   const int32_t a = d;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
   const bool iso = P->mode == 0;
@@ -688,29 +700,48 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   const int lane = threadIdx.x & 63;
   int32_t* wl = s_pool + (threadIdx.x >> 6) * kWaveList;
   unsigned long long my_count = 0;
-  const int64_t ntiles = (w_end - w_begin + kExpandTile - 1) / kExpandTile;
+  const int64_t ntiles = LONG ? w_end : (w_end - w_begin + kExpandTile - 1) / kExpandTile;
   for (int64_t t = xcd_block_id(); t < ntiles; t += gridDim.x) {
-    const int64_t tb = w_begin + t * kExpandTile;
-    const int64_t te = (tb + kExpandTile < w_end) ? tb + kExpandTile : w_end;
-    if (threadIdx.x < 128) {
-      // wave 0: first row of the tile, wave 1: last row (last i with off[i] <= key)
-      const int64_t key = threadIdx.x < 64 ? tb : te - 1;
-      const int32_t x = wave_bound<int64_t>(off, 0, r, key, true) - 1;
-      if (lane == 0) s_misc[threadIdx.x >> 6] = x;
+    int64_t tb, te;  // packed: work items [tb, te); row tiles: list entries [tb, te)
+    int32_t r_lo, r_hi;
+    if (LONG) {
+      if (threadIdx.x < 64) {
+        const int32_t x = wave_bound<int64_t>(toff, 0, r, t, true) - 1;
+        if (lane == 0) s_misc[0] = x;
+      }
+      __syncthreads();
+      r_lo = r_hi = s_misc[0];
+      const int64_t len = off[r_lo + 1] - off[r_lo];
+      tb = (t - toff[r_lo]) * kExpandTile;
+      te = tb + kExpandTile < len ? tb + kExpandTile : len;
+    } else {
+      tb = w_begin + t * kExpandTile;
+      te = (tb + kExpandTile < w_end) ? tb + kExpandTile : w_end;
+      if (threadIdx.x < 128) {
+        // wave 0: first row of the tile, wave 1: last row (last i with off[i] <= key)
+        const int64_t key = threadIdx.x < 64 ? tb : te - 1;
+        const int32_t x = wave_bound<int64_t>(off, 0, r, key, true) - 1;
+        if (lane == 0) s_misc[threadIdx.x >> 6] = x;
+      }
+      __syncthreads();
+      r_lo = s_misc[0];
+      r_hi = s_misc[1];
     }
-    __syncthreads();
-    const int32_t r_lo = s_misc[0], r_hi = s_misc[1];
     const int32_t nrow = r_hi - r_lo + 1;
     const bool single = nrow == 1;
     const bool use_lds = nrow <= kExpandTile;
     const bool rows_lds = use_lds && nrow * d <= kLdsRowInts;
     if (use_lds) {
-      for (int32_t i = threadIdx.x; i <= nrow; i += kBlock) s_off[i] = off[r_lo + i];
+      if (!LONG)
+        for (int32_t i = threadIdx.x; i <= nrow; i += kBlock) s_off[i] = off[r_lo + i];
       for (int32_t i = threadIdx.x; i < nrow; i += kBlock) s_piv[i] = piv[r_lo + i];
       if (rows_lds)
         for (int32_t i = threadIdx.x; i < nrow * d; i += kBlock)
           s_rows[i] = rows[(int64_t)r_lo * d + i];
     }
+    // first and last list entry of the tile (single-row tiles)
+    const int64_t jb = LONG ? tb : tb - off[r_lo];
+    const int32_t nt = (int32_t)(te - tb);
     if (single && threadIdx.x == 0) {
       const int2 pv = piv[r_lo];
       const int32_t b = pv.x >> 2;
@@ -722,15 +753,16 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         if (arc_out ? !(q == b && !vo) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);
       }
       s_misc[2] = n;
-      const int64_t o = off[r_lo];
       const int32_t* list = (pv.x & 2) ? fpool : (vo ? g.out_nbrs : g.in_nbrs);
-      s_misc[3] = list[pv.y + (int32_t)(tb - o)];
-      s_misc[4] = list[pv.y + (int32_t)(te - 1 - o)];
+      s_misc[3] = list[pv.y + (int32_t)jb];
+      s_misc[4] = list[pv.y + (int32_t)jb + nt - 1];
     }
     __syncthreads();
     int32_t ncons = 0;
+    bool bitmap = false;
     if (single) {
       ncons = s_misc[2];
+      bitmap = tile_bitmap(s_misc[3], s_misc[4]);
       // each wavefront cuts the lists of some relations to [cmin, cmax]
       for (int32_t ci = threadIdx.x >> 6; ci < ncons; ci += kWaves) {
         const int32_t desc = s_cons[ci];
@@ -746,30 +778,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(
           s_whi[ci] = whi;
         }
       }
-      __syncthreads();
-      if (!tile_bitmap(s_misc[3], s_misc[4])) {
-        if (threadIdx.x == 0) {
-          int32_t acc = 0;
-          for (int32_t ci = 0; ci < ncons; ++ci) {
-            const int32_t len = s_whi[ci] - s_wlo[ci];
-            if (acc + len <= kTilePool) {
-              s_woff[ci] = acc;
-              acc += len;
-            } else {
-              s_woff[ci] = -1;
-            }
-          }
-        }
-        __syncthreads();
-        for (int32_t ci = 0; ci < ncons; ++ci) {
-          const int32_t woff = s_woff[ci];
-          if (woff < 0) continue;
-          const int32_t* lst = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
-          const int32_t lo = s_wlo[ci], len = s_whi[ci] - lo;
-          for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = lst[lo + x];
-        }
-        __syncthreads();
+      if (!bitmap && ncons > 0) {
+        // the tile's candidates, in list order, for marking
+        const int2 pv = s_piv[0];
+        const int32_t* list = (pv.x & 2) ? fpool : ((pv.x & 1) ? g.out_nbrs : g.in_nbrs);
+        for (int32_t x = threadIdx.x; x < nt; x += kBlock) s_cand[x] = list[pv.y + (int32_t)jb + x];
       }
+      __syncthreads();
     }
 
     int32_t cand[kExpandItems], crow[kExpandItems];
@@ -782,9 +797,12 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       int32_t i = r_lo, li = 0, c = 0, b = 0, pos = 0;
       bool via_out = false, filtered = false;
       if (valid) {
-        int64_t oi;
+        int64_t j;
         int2 pv;
-        if (use_lds) {
+        if (LONG) {
+          j = w;
+          pv = s_piv[0];
+        } else if (use_lds) {
           int32_t lo = 0, hi = nrow - 1;
           while (lo < hi) {
             const int32_t mid = lo + ((hi - lo + 1) >> 1);
@@ -795,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
           }
           li = lo;
           i = r_lo + lo;
-          oi = s_off[lo];
+          j = w - s_off[lo];
           pv = s_piv[lo];
         } else {
           int32_t lo = r_lo, hi = r_hi;
@@ -807,13 +825,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(
               hi = mid - 1;
           }
           i = lo;
-          oi = off[lo];
+          j = w - off[lo];
           pv = piv[lo];
         }
         b = pv.x >> 2;
         via_out = (pv.x & 1) != 0;
         filtered = (pv.x & 2) != 0;
-        pos = pv.y + (int32_t)(w - oi);
+        pos = pv.y + (int32_t)j;
         c = filtered ? fpool[pos] : (via_out ? g.out_nbrs[pos] : g.in_nbrs[pos]);
       }
       cand[it] = c;
@@ -892,17 +910,18 @@ __global__ __launch_bounds__(kBlock) void k_expand(
     }
 
     if (single) {
-      // Relations of the new position, one at a time for the whole tile.  With
-      // the candidate ids spanning at most 32*kTilePool values, the list window
-      // becomes an LDS bitmap over [cmin, cmax] (bit set: the arc exists and
-      // passes its predicate) and each candidate tests one bit; otherwise the
-      // staged windows (or the cut global lists) are binary-searched.
+      // Relations of the new position, one at a time for the whole tile.  A
+      // hit is an arc that exists and passes its predicate; required arcs
+      // keep the hits, absent ones (induced isomorphism) drop them.  With the
+      // candidate ids spanning at most 32*kTilePool values the window of the
+      // list becomes an LDS bitmap over [cmin, cmax]; else a window of at most
+      // kMarkEntries entries marks the tile positions of its entries among the
+      // staged candidates; else candidates binary-search the window.
       const int32_t cmin = s_misc[3];
-      const bool bitmap = tile_bitmap(cmin, s_misc[4]);
       const int32_t words = (int32_t)(((int64_t)s_misc[4] - cmin) >> 5) + 1;
       uint32_t* bm = reinterpret_cast<uint32_t*>(s_pool);
       for (int32_t ci = 0; ci < ncons; ++ci) {
-        if (!__syncthreads_or(keep != 0)) break;  // also orders reuse of the bitmap
+        if (!__syncthreads_or(keep != 0)) break;  // also orders reuse of the bitmaps
         const int32_t desc = s_cons[ci];
         const int q = desc & 31;
         const bool in_dir = ((desc >> 5) & 1) != 0;
@@ -910,36 +929,33 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         const int32_t wlo = s_wlo[ci], whi = s_whi[ci];
         const int32_t* lst = in_dir ? g.in_nbrs : g.out_nbrs;
         const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
-        if (bitmap) {
-          for (int32_t x = threadIdx.x; x < words; x += kBlock) bm[x] = 0u;
+        if (bitmap || whi - wlo <= kMarkEntries) {
+          const int32_t nw = bitmap ? words : (kExpandTile >> 5);
+          uint32_t* mk = bitmap ? bm : s_mark;
+          for (int32_t x = threadIdx.x; x < nw; x += kBlock) mk[x] = 0u;
           __syncthreads();
           for (int32_t x = wlo + threadIdx.x; x < whi; x += kBlock) {
-            const int32_t e = lst[x] - cmin;
+            const int32_t e = lst[x];
+            const int32_t o = bitmap ? e - cmin : lds_find(s_cand, nt, e);
+            if (o < 0) continue;
             bool pass = true;
             if (need) pass = in_dir ? arc_ok_in(g, P, a, q, x) : arc_ok(g, P, q, a, x);
-            if (pass) atomicOr(&bm[e >> 5], 1u << (e & 31));
+            if (pass) atomicOr(&mk[o >> 5], 1u << (o & 31));
           }
           __syncthreads();
 #pragma unroll
           for (int it = 0; it < kExpandItems; ++it) {
             if ((keep >> it) & 1u) {
-              const int32_t o = cand[it] - cmin;
-              const bool hit = ((bm[o >> 5] >> (o & 31)) & 1u) != 0;
+              const int32_t o = bitmap ? cand[it] - cmin : it * kBlock + (int32_t)threadIdx.x;
+              const bool hit = ((mk[o >> 5] >> (o & 31)) & 1u) != 0;
               if (hit != req) keep &= ~(1u << it);
             }
           }
         } else {
-          const int32_t woff = s_woff[ci];
 #pragma unroll
           for (int it = 0; it < kExpandItems; ++it) {
             if ((keep >> it) & 1u) {
-              int32_t pos;
-              if (woff >= 0) {
-                const int32_t x = lds_find(s_pool + woff, whi - wlo, cand[it]);
-                pos = x >= 0 ? wlo + x : -1;
-              } else {
-                pos = find_in(lst, wlo, whi, cand[it]);
-              }
+              const int32_t pos = find_in(lst, wlo, whi, cand[it]);
               bool ok;
               if (!req)
                 ok = pos < 0;
@@ -988,6 +1004,39 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   if (OUT != 0) {
     const unsigned long long tot = block_sum<unsigned long long>(my_count, s_scan);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// Rows with at least kAlignMin candidates get tiles of their own: soff[i] is
+// the length of a shorter row (0 for a long one), toff[i] the tile count of a
+// long row (0 for a short one); per-block sums go to sbsum / tbsum for
+// launch_scan_lengths (same tiling as k_row_pivot).
+__global__ __launch_bounds__(kBlock) void k_split_rows(const int64_t* __restrict__ off, int32_t r,
+                                                       int64_t* __restrict__ soff,
+                                                       int64_t* __restrict__ toff,
+                                                       int64_t* __restrict__ sbsum,
+                                                       int64_t* __restrict__ tbsum) {
+  __shared__ int64_t s_scan[kWaves + 1];
+  int64_t ss = 0, ts = 0;
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+    if (i < r) {
+      const int64_t len = off[i + 1] - off[i];
+      const bool lng = len >= kAlignMin;
+      const int64_t sl = lng ? 0 : len;
+      const int64_t tl = lng ? (len + kExpandTile - 1) / kExpandTile : 0;
+      soff[i] = sl;
+      toff[i] = tl;
+      ss += sl;
+      ts += tl;
+    }
+  }
+  const int64_t a = block_sum<int64_t>(ss, s_scan);
+  const int64_t b = block_sum<int64_t>(ts, s_scan);
+  if (threadIdx.x == 0) {
+    sbsum[blockIdx.x] = a;
+    tbsum[blockIdx.x] = b;
   }
 }
 
@@ -1303,25 +1352,40 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
-                         int out_mode, int32_t* out, unsigned long long* cursor,
-                         unsigned long long out_cap, unsigned long long* partials, int grid,
-                         hipStream_t stream) {
+                         const int64_t* toff, int out_mode, int32_t* out,
+                         unsigned long long* cursor, unsigned long long out_cap,
+                         unsigned long long* partials, int grid, hipStream_t stream) {
   if (w_end <= w_begin || r <= 0) return hipSuccess;
+#define HPM_EXPAND(O, L)                                                                    \
+  k_expand<O, L><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r, \
+                                              w_begin, w_end, toff, out, cursor, out_cap,  \
+                                              partials)
+  const bool lng = toff != nullptr;
   switch (out_mode) {
     case 0:
-      k_expand<0><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
-                                               w_begin, w_end, out, cursor, out_cap, partials);
+      if (lng) HPM_EXPAND(0, true); else HPM_EXPAND(0, false);
       break;
     case 1:
-      k_expand<1><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
-                                               w_begin, w_end, out, cursor, out_cap, partials);
+      if (lng) HPM_EXPAND(1, true); else HPM_EXPAND(1, false);
       break;
     default:
-      k_expand<2><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
-                                               w_begin, w_end, out, cursor, out_cap, partials);
+      if (lng) HPM_EXPAND(2, true); else HPM_EXPAND(2, false);
       break;
   }
+#undef HPM_EXPAND
   return hipGetLastError();
+}
+
+hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64_t* toff,
+                             int64_t* sbsum, int64_t* tbsum, hipStream_t stream) {
+  if (r <= 0) return hipSuccess;
+  const int nb = (int)(((int64_t)r + kPivotTile - 1) / kPivotTile);
+  k_split_rows<<<nb, kBlock, 0, stream>>>(off, r, soff, toff, sbsum, tbsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan_lengths(soff, r, sbsum, stream);
+  if (e != hipSuccess) return e;
+  return launch_scan_lengths(toff, r, tbsum, stream);
 }
 
 hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,

@@ -107,6 +107,8 @@ struct Workspace {
   // sums; shared by all depths the hash table and slot descriptors
   DevBuf fpool[kMaxK], off2[kMaxK];
   DevBuf fkeys, fdense, fslot_key, fslot_region, fcount;
+  // per depth: prefix sums of short-row lengths and of long-row tile counts
+  DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
   unsigned long long* host = nullptr;  // pinned readback slots
   DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
   std::vector<hipEvent_t> events;
@@ -121,7 +123,7 @@ struct Workspace {
                fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
-           off2[d].bytes;
+           off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
     return s;
   }
   void release_all() {
@@ -132,6 +134,7 @@ struct Workspace {
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
       fpool[d].release(); off2[d].release();
+      soff[d].release(); toff[d].release(); sbsum[d].release(); tbsum[d].release();
     }
   }
 };
@@ -417,8 +420,14 @@ DevPlan build_dev_plan(const hpm_pattern* p, const PatternInfo& P, const std::ve
 
 enum : int {
   kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3, kCntSlots = 4,
-  kCntFilterSlots = 5, kCntFilterPool = 6
+  kCntFilterSlots = 5, kCntFilterPool = 6,
+  kHostSplit = 8,   // pinned readback slots 8, 9: short work and long tiles of a split
+  kHostSlots = 16
 };
+
+// Split rows into packed short rows and row-aligned long rows only when a
+// depth has at least this many candidates.
+constexpr int64_t kSplitMinWork = int64_t(1) << 16;
 
 // Pre-filter pivot lists only when a depth has at least this many candidates.
 constexpr int64_t kFilterMinWork = int64_t(1) << 22;
@@ -594,6 +603,41 @@ struct Matcher {
     st.filtered_lists += (uint64_t)nslots;
   }
 
+  // Extra bytes ensure(want) would allocate for b.
+  static uint64_t growth(const DevBuf& b, uint64_t want) { return want > b.bytes ? want : 0; }
+
+  // Separate rows with at least kAlignMin candidates (row-aligned tiles) from
+  // the rest (packed tiles).  On success *S is the short rows' work and *T the
+  // long rows' tile count (W->soff[d] / W->toff[d] hold the prefix sums).
+  bool split_rows(int32_t d, int64_t r, const int64_t* offp, int64_t work, int64_t* S,
+                  int64_t* T) {
+    if (work < kSplitMinWork) return false;
+    const uint64_t nb = ((uint64_t)r + hpm::kPivotTile - 1) / hpm::kPivotTile + 1;
+    const uint64_t pre = (uint64_t)(r + 1) * sizeof(int64_t);
+    const uint64_t more = growth(W->soff[d], pre) + growth(W->toff[d], pre) +
+                          growth(W->sbsum[d], nb * 8) + growth(W->tbsum[d], nb * 8);
+    if (W->held() + more > budget) return false;
+    W->soff[d].ensure(pre, stream);
+    W->toff[d].ensure(pre, stream);
+    W->sbsum[d].ensure(nb * 8, stream);
+    W->tbsum[d].ensure(nb * 8, stream);
+    int64_t* so = W->soff[d].as<int64_t>();
+    int64_t* to = W->toff[d].as<int64_t>();
+    launch(HPM_K_PREFIX_SUM, [&] {
+      return hpm::launch_split_rows(offp, (int32_t)r, so, to, W->sbsum[d].as<int64_t>(),
+                                    W->tbsum[d].as<int64_t>(), stream);
+    });
+    hip_check(hipMemcpyAsync(W->host + kHostSplit, so + r, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, stream), "readback");
+    hip_check(hipMemcpyAsync(W->host + kHostSplit + 1, to + r, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, stream), "readback");
+    sync();
+    *S = (int64_t)W->host[kHostSplit];
+    *T = (int64_t)W->host[kHostSplit + 1];
+    if (*S > work || *T > work) fail(HPM_E_INTERNAL, "row split overflow");
+    return *T > 0;
+  }
+
   // Extend the r rows (each d entries) in `rows` to full embeddings.
   void process_depth(int32_t d, const int32_t* rows, int64_t r) {
     if (r == 0) return;
@@ -613,20 +657,59 @@ struct Matcher {
     st.work[d] += (uint64_t)work;
     if (work == 0) return;
     if (d == k - 1) {
-      const int grid = grid_for(work, hpm::kExpandTile);
+      int64_t S = work, T = 0;
+      const bool split = split_rows(d, r, offp, work, &S, &T);
+      const int64_t* soffp = split ? W->soff[d].as<int64_t>() : offp;
+      const int g1 = S > 0 ? grid_for(S, hpm::kExpandTile) : 0;
+      const int g2 = T > 0 ? grid_for(T * hpm::kExpandTile, hpm::kExpandTile) : 0;
       const int mode = maps ? 2 : 1;
-      launch(HPM_K_LAST_LEVEL, [&] {
-        return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
-                                  fpool, (int32_t)r, 0, work, mode, maps, counters() + kCntEmit,
-                                  maps ? emit_cap() : 0, W->partials.as<unsigned long long>(),
-                                  grid, stream);
-      });
+      unsigned long long* parts = W->partials.as<unsigned long long>();
+      if (g1)
+        launch(HPM_K_LAST_LEVEL, [&] {
+          return hpm::launch_expand(g, dplan(), bits(d), d, rows, soffp, piv, fpool, (int32_t)r,
+                                    0, S, nullptr, mode, maps, counters() + kCntEmit,
+                                    maps ? emit_cap() : 0, parts, g1, stream);
+        });
+      if (g2)
+        launch(HPM_K_LAST_LEVEL, [&] {
+          return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r,
+                                    0, T, W->toff[d].as<int64_t>(), mode, maps,
+                                    counters() + kCntEmit, maps ? emit_cap() : 0, parts + g1, g2,
+                                    stream);
+        });
       launch(HPM_K_REDUCE, [&] {
-        return hpm::launch_reduce_counts(W->partials.as<unsigned long long>(), grid,
-                                         counters() + kCntTotal,
+        return hpm::launch_reduce_counts(parts, g1 + g2, counters() + kCntTotal,
                                          reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
                                          stream);
       });
+      return;
+    }
+    int64_t S = work, T = 0;
+    if (work <= chunk && split_rows(d, r, offp, work, &S, &T)) {
+      // the whole depth in one piece: packed short rows and row-aligned long rows
+      st.chunks++;
+      W->rows[d + 1].ensure((size_t)work * (d + 1) * sizeof(int32_t), stream);
+      ensure_depth(d + 1, work);
+      int32_t* out = W->rows[d + 1].as<int32_t>();
+      zero_counter(kCntCursor);
+      if (S > 0)
+        launch(HPM_K_EXPAND, [&] {
+          return hpm::launch_expand(g, dplan(), bits(d), d, rows, W->soff[d].as<int64_t>(), piv,
+                                    fpool, (int32_t)r, 0, S, nullptr, 0, out,
+                                    counters() + kCntCursor, (unsigned long long)work,
+                                    W->partials.as<unsigned long long>(),
+                                    grid_for(S, hpm::kExpandTile), stream);
+        });
+      launch(HPM_K_EXPAND, [&] {
+        return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r, 0,
+                                  T, W->toff[d].as<int64_t>(), 0, out, counters() + kCntCursor,
+                                  (unsigned long long)work, W->partials.as<unsigned long long>(),
+                                  grid_for(T * hpm::kExpandTile, hpm::kExpandTile), stream);
+      });
+      const int64_t r1 = (int64_t)read_counter(kCntCursor);
+      if (r1 > work) fail(HPM_E_INTERNAL, "frontier overflow");
+      process_depth(d + 1, out, r1);
+      check_limit();
       return;
     }
     for (int64_t w0 = 0; w0 < work && !stopped; w0 += chunk) {
@@ -640,8 +723,8 @@ struct Matcher {
       const int grid = grid_for(n_items, hpm::kExpandTile);
       launch(HPM_K_EXPAND, [&] {
         return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
-                                  fpool, (int32_t)r, w0, w1, 0, out, counters() + kCntCursor,
-                                  (unsigned long long)n_items,
+                                  fpool, (int32_t)r, w0, w1, nullptr, 0, out,
+                                  counters() + kCntCursor, (unsigned long long)n_items,
                                   W->partials.as<unsigned long long>(), grid, stream);
       });
       const int64_t r1 = (int64_t)read_counter(kCntCursor);
@@ -1000,7 +1083,8 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       W->release_all();
     }
     if (!W->host)
-      hip_check(hipHostMalloc((void**)&W->host, 8 * sizeof(unsigned long long)), "hipHostMalloc");
+      hip_check(hipHostMalloc((void**)&W->host, kHostSlots * sizeof(unsigned long long)),
+                "hipHostMalloc");
     if (!W->host_plan)
       hip_check(hipHostMalloc((void**)&W->host_plan, sizeof(DevPlan)), "hipHostMalloc");
 
@@ -1013,7 +1097,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     W->plan.ensure(sizeof(DevPlan), stream);
     W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t), stream);
     W->counters.ensure(8 * sizeof(unsigned long long), stream);
-    W->partials.ensure((size_t)max_grid * sizeof(unsigned long long), stream);
+    W->partials.ensure((size_t)max_grid * 2 * sizeof(unsigned long long), stream);
     if (k >= 3) {
       const int64_t rows2 = std::min<int64_t>(cap2, std::max<int64_t>(G->m, 1));
       W->rows2.ensure((size_t)rows2 * 2 * sizeof(int32_t), stream);
