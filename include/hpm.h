@@ -134,7 +134,9 @@ typedef struct {
   uint32_t struct_size;      /* sizeof(hpm_match_opts); 16 = the layout without
                                 max_matches (treated as 0)                     */
   uint32_t flags;            /* HPM_F_*                                        */
-  uint64_t hbm_budget_bytes; /* scratch limit; 0 = 25% of free device memory   */
+  uint64_t hbm_budget_bytes; /* scratch limit; 0 = 25% of the device memory
+                                that is free or already held as this graph's
+                                idle scratch                                  */
   uint64_t max_matches;      /* first-k: stop once this many embeddings are
                                 found (0 = find all).  *count is then
                                 min(total, max_matches) and the mapping rows
@@ -159,9 +161,11 @@ typedef struct {
  *           order is unspecified.
  * cap       rows available in mappings (ignored when mappings is NULL).
  *
- * The scratch space (partial-mapping frontiers) is bounded by
+ * The scratch space (partial-mapping frontiers) the call uses is bounded by
  * opts->hbm_budget_bytes; the frontier is expanded in chunks that fit it, so the
- * result never depends on the budget.  Several calls may run concurrently on
+ * result never depends on the budget.  Scratch is kept between calls on a
+ * graph for reuse; idle scratch beyond twice a call's budget is freed when
+ * that call starts.  Several calls may run concurrently on
  * different streams with the same graph.
  * Errors: HPM_E_ARG, HPM_E_PATTERN (invalid pattern or column-count mismatch),
  * HPM_E_NOMEM (budget below the minimum chunk, or allocation failure),

@@ -131,10 +131,12 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 // toff NULL: packed tiles over work items [w_begin, w_end) of the prefix sums
 // off.  toff non-NULL: w_end tiles of long rows (toff = their tile prefix sums
 // from launch_split_rows, off = the full length prefix sums).
+// done: positions whose relations with position d the pre-filtered lists
+// already enforce (rows with pivot code bit 1 skip them).
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
-                         const int64_t* toff, int out_mode, int32_t* out,
+                         const int64_t* toff, uint32_t done, int out_mode, int32_t* out,
                          unsigned long long* cursor, unsigned long long out_cap,
                          unsigned long long* partials, int grid, hipStream_t stream);
 // Split rows by list length (prefix sums off[0..r]): soff[0..r] = prefix sums
@@ -143,26 +145,42 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
 // launch_scan_lengths.
 hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64_t* toff,
                              int64_t* sbsum, int64_t* tbsum, hipStream_t stream);
-// Pivot-list filter.  off: the rows' exclusive length prefix sums.  keys[H]
-// must hold ~0 (empty) on entry, H a power of two above the number of rows
-// with a list of >= min_len entries.  Inserts their keys, then numbers the
-// distinct keys: counters[0] += slots, counters[1] += pool entries reserved;
-// slot_key / slot_region [H] describe each slot, dense[H] maps table slots.
-hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
-                              const int2* piv, const int64_t* off, int32_t min_len,
-                              unsigned long long* keys, uint32_t H, int32_t* dense,
-                              unsigned long long* slot_key, int64_t* slot_region,
-                              unsigned long long* counters, hipStream_t stream);
+// Pivot-list filter.  off: the rows' exclusive length prefix sums.  Rows with
+// a list of >= min_len entries are grouped by key: table 0 by pivot list and,
+// when rmask != 0, table 1 by the images of the positions in rmask (every
+// position related to the new one).  Each table has H slots (a power of two
+// above the number of such rows), table t at keys + t * H; keys must hold ~0
+// (empty) on entry.  distinct[t] += keys of table t.
+hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
+                                const int64_t* off, int32_t min_len, uint32_t rmask,
+                                unsigned long long* keys, uint32_t H,
+                                unsigned long long* distinct, hipStream_t stream);
+// Number the groups of one table (keys[H]; rmask 0 for table 0, else the
+// table-1 mask with rep[H] holding INT32_MAX on entry): dense[H] maps slots to
+// groups, slot_key (table 0) or slot_rep (table 1, the group's smallest row)
+// and slot_region describe each group; counters[0] += groups, counters[1] +=
+// pool entries reserved (raw list lengths).
+hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
+                                const int2* piv, const int64_t* off, int32_t min_len,
+                                uint32_t rmask, const unsigned long long* keys, uint32_t H,
+                                int32_t* rep, int32_t* dense, unsigned long long* slot_key,
+                                int32_t* slot_rep, int64_t* slot_region,
+                                unsigned long long* counters, hipStream_t stream);
+// One block per group: the filtered list into pool + slot_region[s], its
+// length into fcount[s].
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
-                               int32_t a, int32_t nslots, const unsigned long long* slot_key,
-                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
-                               hipStream_t stream);
-// New list lengths into len[0..r) (+ block sums), long rows redirected in piv.
+                               int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
+                               int32_t nslots, const unsigned long long* slot_key,
+                               const int32_t* slot_rep, const int64_t* slot_region,
+                               int32_t* pool, int32_t* fcount, hipStream_t stream);
+// New list lengths into len[0..r) (+ block sums), grouped rows redirected in
+// piv (code bit 1); a row whose images differ from its group's representative
+// stays as it is.
 hipError_t launch_filter_apply(const int32_t* rows, int32_t r, int32_t d, int2* piv,
-                               const int64_t* off, int64_t* len, int32_t min_len,
+                               const int64_t* off, int64_t* len, int32_t min_len, uint32_t rmask,
                                const unsigned long long* keys, uint32_t H, const int32_t* dense,
-                               const int64_t* slot_region, const int32_t* fcount, int64_t* bsum,
-                               hipStream_t stream);
+                               const int32_t* slot_rep, const int64_t* slot_region,
+                               const int32_t* fcount, int64_t* bsum, hipStream_t stream);
 // total[0] += sum(partials[0..nparts)); overflow[0] |= 1 on uint64 wrap.
 hipError_t launch_reduce_counts(const unsigned long long* partials, int32_t nparts,
                                 unsigned long long* total, uint32_t* overflow, hipStream_t stream);

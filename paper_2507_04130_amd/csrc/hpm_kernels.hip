@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
     DevGraph g, const DevPlan* __restrict__ P, const uint32_t* __restrict__ abits, int32_t d,
     const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
     const int2* __restrict__ piv, const int32_t* __restrict__ fpool, int32_t r, int64_t w_begin,
-    int64_t w_end, const int64_t* __restrict__ toff, int32_t* __restrict__ out,
+    int64_t w_end, const int64_t* __restrict__ toff, uint32_t done, int32_t* __restrict__ out,
     unsigned long long* __restrict__ cursor, unsigned long long out_cap,
     unsigned long long* __restrict__ partials) {
   // Packed tiles (LONG false): work item w in [w_begin, w_end) is candidate
@@ -669,6 +669,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   // Row tiles (LONG true): w_end tiles; tile t is segment s = t - toff[i] of the
   // row i with toff[i] <= t < toff[i+1], i.e. entries [s, s+1) * kExpandTile
   // (cut at the row's length off[i+1] - off[i]) of that row's list.
+  // done: positions whose relations with the new one a pre-filtered list
+  // (pivot code bit 1) has already checked.
   //
   // Membership tests (is f(q) -> c an arc?) go three ways:
   //  * tile inside one row (every row tile; packed tiles of long lists): the
@@ -746,8 +748,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       const int2 pv = piv[r_lo];
       const int32_t b = pv.x >> 2;
       const bool vo = (pv.x & 1) != 0;
+      const uint32_t skip = (pv.x & 2) ? done : 0u;
       int32_t n = 0;
       for (int q = 0; q < d; ++q) {
+        if ((skip >> q) & 1u) continue;
         const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
         if (arc_in ? !(q == b && vo) : iso) s_cons[n++] = pack_cons(q, 0, arc_in);
         if (arc_out ? !(q == b && !vo) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);
@@ -863,10 +867,12 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         if (same_row) {
           const int32_t b0 = __shfl(b, 0);
           const bool vo0 = __shfl((int)via_out, 0) != 0;
+          const uint32_t skip0 = __shfl((int)filtered, 0) ? done : 0u;
           const int32_t cmin = __shfl(c, 0);
           const int32_t cmax = __shfl(c, 63 - __clzll((long long)vmask));
           for (int q = 0; q < d; ++q) {
             if (!__any(ok)) break;  // wave-uniform
+            if ((skip0 >> q) & 1u) continue;
             const int32_t fq = __shfl(rowv(q), 0);
             const bool arc_in = (fw >> q) & 1u;   // pattern arc q -> a
             const bool arc_out = (bw >> q) & 1u;  // pattern arc a -> q
@@ -882,7 +888,9 @@ __global__ __launch_bounds__(kBlock) void k_expand(
             }
           }
         } else {
+          const uint32_t skip = filtered ? done : 0u;
           for (int q = 0; q < d && ok; ++q) {
+            if ((skip >> q) & 1u) continue;
             const int32_t fq = rowv(q);
             // pattern arc q -> a  <=>  target arc f(q) -> c  (=> only, for monomorphism)
             if ((fw >> q) & 1u) {
@@ -1043,14 +1051,35 @@ __global__ __launch_bounds__(kBlock) void k_split_rows(const int64_t* __restrict
 // ------------------------------------------------------------ pivot-list filter
 //
 // Rows of one depth often share a long pivot list (many partial mappings
-// extend the same hub).  Each distinct long list -- key (vertex, direction,
-// pivot position) -- is filtered once: the candidates that pass the vertex
-// validator of the new position and the predicate of the pivot arc, in list
-// order, go to a pool; the rows are then pointed at their filtered list.
+// extend the same hub).  Rows are grouped by a key and each group's list is
+// filtered once; the candidates that pass, in list order, go to a pool and
+// the rows are pointed at their filtered list.
+//  * rmask == 0: the key is the pivot list itself (vertex, direction, pivot
+//    position); the filter applies the vertex validator of the new position
+//    and the predicate of the pivot arc.
+//  * rmask != 0: the key is the images of the positions in rmask, which are
+//    all the mapped positions related to the new one by a pattern arc (the
+//    pivot is one of them and is chosen from them alone, so equal keys give
+//    equal pivots).  The filter applies, besides, every condition between the
+//    new position and those positions (Eq. (1)-(3) for that pair), so the
+//    extension of such a row only checks injectivity and, for induced
+//    isomorphism, non-arcs to the other positions.
+// Keys of the second kind are 64-bit hashes; each group keeps its smallest
+// row as representative and a row whose images differ from its group's
+// representative (a hash collision) is simply left unfiltered.
 
 __device__ __forceinline__ uint64_t pivot_key(int32_t v, int32_t code) {
   // vertex | direction bit | pivot position
   return (uint64_t)(uint32_t)v | ((uint64_t)(code & 1) << 32) | ((uint64_t)(code >> 2) << 33);
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
 }
 
 __device__ __forceinline__ uint32_t key_hash(uint64_t x) {
@@ -1062,6 +1091,16 @@ __device__ __forceinline__ uint32_t key_hash(uint64_t x) {
 
 constexpr unsigned long long kEmptyKey = ~0ull;
 
+// Group key of row i (see above).
+__device__ __forceinline__ unsigned long long row_key(const int32_t* __restrict__ rows, int64_t i,
+                                                      int32_t d, int32_t code, uint32_t rmask) {
+  if (rmask == 0) return pivot_key(rows[i * d + (code >> 2)], code);
+  uint64_t h = 0x243f6a8885a308d3ull;
+  for (int q = 0; q < d; ++q)
+    if ((rmask >> q) & 1u) h = mix64(h ^ ((uint64_t)(uint32_t)rows[i * d + q] + ((uint64_t)q << 32)));
+  return h == kEmptyKey ? kEmptyKey - 1 : h;
+}
+
 // Slot of key in the open-addressing table (keys[H], H a power of two).
 __device__ __forceinline__ uint32_t table_find(const unsigned long long* __restrict__ keys,
                                                uint32_t H, unsigned long long key) {
@@ -1071,81 +1110,244 @@ __device__ __forceinline__ uint32_t table_find(const unsigned long long* __restr
 }
 
 // off: exclusive prefix sums of the rows' list lengths (off[r] = total).
+// Table 0 (keys[0..H)) groups by pivot list; with rmask != 0 table 1
+// (keys[H..2H)) groups by the images of the positions in rmask.
+// distinct[t] counts the keys of table t.
 __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restrict__ rows,
                                                           int32_t r, int32_t d,
                                                           const int2* __restrict__ piv,
                                                           const int64_t* __restrict__ off,
-                                                          int32_t min_len,
+                                                          int32_t min_len, uint32_t rmask,
                                                           unsigned long long* __restrict__ keys,
-                                                          uint32_t H) {
+                                                          uint32_t H,
+                                                          unsigned long long* __restrict__ distinct) {
+  const int ntab = rmask ? 2 : 1;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
        i += (int64_t)gridDim.x * kBlock) {
     if (off[i + 1] - off[i] < min_len) continue;
-    const int32_t code = piv[i].x;
-    const unsigned long long key = pivot_key(rows[i * d + (code >> 2)], code);
-    uint32_t h = key_hash(key) & (H - 1);
-    while (true) {  // H exceeds the number of rows, so a free slot exists
-      const unsigned long long prev = atomicCAS(&keys[h], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) break;
-      h = (h + 1) & (H - 1);
+    for (int t = 0; t < ntab; ++t) {
+      unsigned long long* tab = keys + (size_t)t * H;
+      const unsigned long long key = row_key(rows, i, d, piv[i].x, t ? rmask : 0u);
+      uint32_t h = key_hash(key) & (H - 1);
+      while (true) {  // H exceeds the number of rows, so a free slot exists
+        const unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
+        if (prev == kEmptyKey) atomicAdd(&distinct[t], 1ull);
+        if (prev == kEmptyKey || prev == key) break;
+        h = (h + 1) & (H - 1);
+      }
     }
   }
 }
 
-// Dense ids and pool regions for the occupied slots.  counters[0] = slots,
-// counters[1] = pool entries reserved (sum of raw list lengths).
+// Table 1: rep[slot] = the smallest row with that key (rep holds INT32_MAX on
+// entry).
+__global__ __launch_bounds__(kBlock) void k_filter_rep(const int32_t* __restrict__ rows,
+                                                       int32_t r, int32_t d,
+                                                       const int2* __restrict__ piv,
+                                                       const int64_t* __restrict__ off,
+                                                       int32_t min_len, uint32_t rmask,
+                                                       const unsigned long long* __restrict__ keys,
+                                                       uint32_t H, int32_t* __restrict__ rep) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
+       i += (int64_t)gridDim.x * kBlock) {
+    if (off[i + 1] - off[i] < min_len) continue;
+    const unsigned long long key = row_key(rows, i, d, piv[i].x, rmask);
+    atomicMin(&rep[table_find(keys, H, key)], (int32_t)i);
+  }
+}
+
+// Dense ids and pool regions for the occupied slots of one table (keys[H]):
+// counters[0] = groups, counters[1] = pool entries reserved (sum of raw list
+// lengths).  Pivot-list groups (rep == NULL) keep their key in slot_key;
+// groups by related images keep their representative row in slot_rep.
 __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
+                                                          const int32_t* __restrict__ rows,
+                                                          int32_t d,
+                                                          const int2* __restrict__ piv,
                                                           const unsigned long long* __restrict__ keys,
-                                                          uint32_t H, int32_t* __restrict__ dense,
+                                                          uint32_t H,
+                                                          const int32_t* __restrict__ rep,
+                                                          int32_t* __restrict__ dense,
                                                           unsigned long long* __restrict__ slot_key,
+                                                          int32_t* __restrict__ slot_rep,
                                                           int64_t* __restrict__ slot_region,
                                                           unsigned long long* __restrict__ counters) {
   for (int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x; h < H;
        h += (int64_t)gridDim.x * kBlock) {
     const unsigned long long key = keys[h];
     if (key == kEmptyKey) continue;
-    const int32_t v = (int32_t)(key & 0xffffffffull);
-    const bool out_dir = ((key >> 32) & 1ull) != 0;
-    const int32_t L = out_dir ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
+    int32_t v, code;
+    if (rep) {
+      const int32_t i = rep[h];
+      code = piv[i].x;
+      v = rows[(int64_t)i * d + (code >> 2)];
+    } else {
+      v = (int32_t)(key & 0xffffffffull);
+      code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+    }
+    const int32_t L = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
     const unsigned long long s = atomicAdd(&counters[0], 1ull);
     dense[h] = (int32_t)s;
-    slot_key[s] = key;
+    if (rep)
+      slot_rep[s] = rep[h];
+    else
+      slot_key[s] = key;
     slot_region[s] = (int64_t)atomicAdd(&counters[1], (unsigned long long)L);
   }
 }
 
-// One block per distinct list: order-preserving compaction of the candidates
-// that pass the vertex validator of position a and the pivot-arc predicate.
+// One block per group: order-preserving compaction of the candidates of the
+// representative row's pivot list that pass the vertex validator of position
+// a, the pivot-arc predicate and (rmask != 0) every condition between a and
+// the positions in rmask.  The list is taken kExpandTile entries at a time
+// (4 consecutive ones per thread); every checked list is cut once per piece
+// to the piece's id range, staged in LDS when short enough and searched
+// there, else searched in the cut range.
 __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
                                                          const uint32_t* __restrict__ abits,
-                                                         int32_t a,
+                                                         int32_t a, const int32_t* __restrict__ rows,
+                                                         const int2* __restrict__ piv,
+                                                         uint32_t rmask,
                                                          const unsigned long long* __restrict__ slot_key,
+                                                         const int32_t* __restrict__ slot_rep,
                                                          const int64_t* __restrict__ slot_region,
                                                          int32_t* __restrict__ pool,
                                                          int32_t* __restrict__ fcount) {
   __shared__ int32_t s_scan[kWaves + 1];
-  const unsigned long long key = slot_key[blockIdx.x];
-  const int32_t v = (int32_t)(key & 0xffffffffull);
-  const bool out_dir = ((key >> 32) & 1ull) != 0;
-  const int32_t b = (int32_t)(key >> 33);
+  __shared__ int32_t s_f[kMaxK];
+  __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
+  __shared__ int32_t s_pool[kTilePool];
+  __shared__ int32_t s_n;
+  const int32_t d = a;
+  int32_t code, pv_v = 0;
+  int64_t i = 0;
+  if (rmask) {
+    i = slot_rep[blockIdx.x];
+    code = piv[i].x;
+  } else {
+    const unsigned long long key = slot_key[blockIdx.x];
+    pv_v = (int32_t)(key & 0xffffffffull);
+    code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+  }
+  const int32_t b = code >> 2;
+  const bool out_dir = (code & 1) != 0;
+  const uint32_t fw = P->fwd[a], bw = P->bwd[a];
+  const bool iso = P->mode == 0;
+  const int lane = threadIdx.x & 63;
+  if (rmask && threadIdx.x < d) s_f[threadIdx.x] = rows[i * d + threadIdx.x];
+  if (threadIdx.x == 0) {
+    // relations checked here: every condition with a position in rmask but
+    // the pivot arc itself
+    int32_t n = 0;
+    for (int q = 0; q < d; ++q) {
+      if (!((rmask >> q) & 1u)) continue;
+      const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
+      if (arc_in ? !(q == b && out_dir) : iso) s_cons[n++] = pack_cons(q, 0, arc_in);
+      if (arc_out ? !(q == b && !out_dir) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);
+    }
+    s_n = n;
+  }
+  __syncthreads();
+  const int32_t ncons = s_n;
+  const int32_t v = rmask ? s_f[b] : pv_v;
   const int32_t lo = out_dir ? g.out_off[v] : g.in_off[v];
   const int32_t hi = out_dir ? g.out_off[v + 1] : g.in_off[v + 1];
   const int32_t* lst = out_dir ? g.out_nbrs : g.in_nbrs;
   int32_t* dst = pool + slot_region[blockIdx.x];
   int32_t run = 0;
-  for (int32_t base = lo; base < hi; base += kBlock) {
-    const int32_t x = base + threadIdx.x;
-    int32_t c = 0;
-    bool ok = false;
-    if (x < hi) {
-      c = lst[x];
-      ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
-      if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok_in(g, P, a, b, x);
+  for (int32_t base = lo; base < hi; base += kExpandTile) {
+    const int32_t end = base + kExpandTile < hi ? base + kExpandTile : hi;
+    int32_t c[kExpandItems];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int it = 0; it < kExpandItems; ++it) {
+      const int32_t x = base + (int32_t)threadIdx.x * kExpandItems + it;
+      c[it] = 0;
+      if (x < end) {
+        const int32_t cc = lst[x];
+        c[it] = cc;
+        bool ok = ((abits[cc >> 5] >> (cc & 31)) & 1u) != 0;
+        if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok_in(g, P, a, b, x);
+        keep |= (uint32_t)ok << it;
+      }
     }
+    if (ncons > 0) {
+      const int32_t cmin = lst[base], cmax = lst[end - 1];
+      // cut every checked list to [cmin, cmax]; stage what fits
+      for (int32_t ci = threadIdx.x >> 6; ci < ncons; ci += kWaves) {
+        const int32_t desc = s_cons[ci];
+        const int32_t fq = s_f[desc & 31];
+        const bool in_dir = ((desc >> 5) & 1) != 0;
+        const int32_t* cl = in_dir ? g.in_nbrs : g.out_nbrs;
+        const int32_t l = in_dir ? g.in_off[fq] : g.out_off[fq];
+        const int32_t h = in_dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+        const int32_t wlo = wave_bound<int32_t>(cl, l, h, cmin, false);
+        const int32_t whi = wave_bound<int32_t>(cl, wlo, h, cmax, true);
+        if (lane == 0) {
+          s_wlo[ci] = wlo;
+          s_whi[ci] = whi;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int32_t ci = 0; ci < ncons; ++ci) {
+          const int32_t len = s_whi[ci] - s_wlo[ci];
+          if (acc + len <= kTilePool) {
+            s_woff[ci] = acc;
+            acc += len;
+          } else {
+            s_woff[ci] = -1;
+          }
+        }
+      }
+      __syncthreads();
+      for (int32_t ci = 0; ci < ncons; ++ci) {
+        const int32_t woff = s_woff[ci];
+        if (woff < 0) continue;
+        const int32_t* cl = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
+        const int32_t wlo = s_wlo[ci], len = s_whi[ci] - wlo;
+        for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = cl[wlo + x];
+      }
+      __syncthreads();
+      for (int32_t ci = 0; ci < ncons; ++ci) {
+        const int32_t desc = s_cons[ci];
+        const int q = desc & 31;
+        const bool in_dir = ((desc >> 5) & 1) != 0;
+        const bool req = ((desc >> 6) & 1) != 0;
+        const int32_t* cl = in_dir ? g.in_nbrs : g.out_nbrs;
+        const int32_t wlo = s_wlo[ci], whi = s_whi[ci], woff = s_woff[ci];
+        const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
+#pragma unroll
+        for (int it = 0; it < kExpandItems; ++it) {
+          if (!((keep >> it) & 1u)) continue;
+          int32_t pos;
+          if (woff >= 0) {
+            const int32_t x = lds_find(s_pool + woff, whi - wlo, c[it]);
+            pos = x >= 0 ? wlo + x : -1;
+          } else {
+            pos = find_in(cl, wlo, whi, c[it]);
+          }
+          bool ok;
+          if (!req)
+            ok = pos < 0;
+          else if (!need)
+            ok = pos >= 0;
+          else
+            ok = pos >= 0 && (in_dir ? arc_ok_in(g, P, a, q, pos) : arc_ok(g, P, q, a, pos));
+          if (!ok) keep &= ~(1u << it);
+        }
+      }
+    }
+    // list order is thread order, then item order: one scan of per-thread counts
     int32_t tot;
-    const int32_t ex = block_exclusive_scan<int32_t>(ok ? 1 : 0, s_scan, &tot);
-    if (ok) dst[run + ex] = c;
+    const int32_t ex = block_exclusive_scan<int32_t>(__popc(keep), s_scan, &tot);
+    int32_t o = run + ex;
+#pragma unroll
+    for (int it = 0; it < kExpandItems; ++it)
+      if ((keep >> it) & 1u) dst[o++] = c[it];
     run += tot;
+    __syncthreads();  // s_wlo / s_pool are rewritten by the next piece
   }
   if (threadIdx.x == 0) fcount[blockIdx.x] = run;
 }
@@ -1158,10 +1360,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_apply(const int32_t* __restri
                                                          int2* __restrict__ piv,
                                                          const int64_t* __restrict__ off,
                                                          int64_t* __restrict__ len,
-                                                         int32_t min_len,
+                                                         int32_t min_len, uint32_t rmask,
                                                          const unsigned long long* __restrict__ keys,
                                                          uint32_t H,
                                                          const int32_t* __restrict__ dense,
+                                                         const int32_t* __restrict__ slot_rep,
                                                          const int64_t* __restrict__ slot_region,
                                                          const int32_t* __restrict__ fcount,
                                                          int64_t* __restrict__ bsum) {
@@ -1174,10 +1377,18 @@ __global__ __launch_bounds__(kBlock) void k_filter_apply(const int32_t* __restri
       int64_t L = off[i + 1] - off[i];
       if (L >= min_len) {
         const int2 pv = piv[i];
-        const unsigned long long key = pivot_key(rows[i * d + (pv.x >> 2)], pv.x);
+        const unsigned long long key = row_key(rows, i, d, pv.x, rmask);
         const int32_t sidx = dense[table_find(keys, H, key)];
-        piv[i] = make_int2(pv.x | 2, (int32_t)slot_region[sidx]);
-        L = fcount[sidx];
+        bool same = true;
+        if (rmask != 0) {
+          const int64_t j = slot_rep[sidx];
+          for (int q = 0; q < d; ++q)
+            if ((rmask >> q) & 1u) same = same && rows[i * d + q] == rows[j * d + q];
+        }
+        if (same) {
+          piv[i] = make_int2(pv.x | 2, (int32_t)slot_region[sidx]);
+          L = fcount[sidx];
+        }
       }
       len[i] = L;
       sum += L;
@@ -1352,14 +1563,14 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,
-                         const int64_t* toff, int out_mode, int32_t* out,
+                         const int64_t* toff, uint32_t done, int out_mode, int32_t* out,
                          unsigned long long* cursor, unsigned long long out_cap,
                          unsigned long long* partials, int grid, hipStream_t stream) {
   if (w_end <= w_begin || r <= 0) return hipSuccess;
 #define HPM_EXPAND(O, L)                                                                    \
   k_expand<O, L><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r, \
-                                              w_begin, w_end, toff, out, cursor, out_cap,  \
-                                              partials)
+                                              w_begin, w_end, toff, done, out, cursor,     \
+                                              out_cap, partials)
   const bool lng = toff != nullptr;
   switch (out_mode) {
     case 0:
@@ -1388,40 +1599,55 @@ hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64
   return launch_scan_lengths(toff, r, tbsum, stream);
 }
 
-hipError_t launch_filter_keys(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
-                              const int2* piv, const int64_t* off, int32_t min_len,
-                              unsigned long long* keys, uint32_t H, int32_t* dense,
-                              unsigned long long* slot_key, int64_t* slot_region,
-                              unsigned long long* counters, hipStream_t stream) {
+hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
+                                const int64_t* off, int32_t min_len, uint32_t rmask,
+                                unsigned long long* keys, uint32_t H,
+                                unsigned long long* distinct, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
-  k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(rows, r, d, piv, off,
-                                                                              min_len, keys, H);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+      rows, r, d, piv, off, min_len, rmask, keys, H, distinct);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t r, int32_t d,
+                                const int2* piv, const int64_t* off, int32_t min_len,
+                                uint32_t rmask, const unsigned long long* keys, uint32_t H,
+                                int32_t* rep, int32_t* dense, unsigned long long* slot_key,
+                                int32_t* slot_rep, int64_t* slot_region,
+                                unsigned long long* counters, hipStream_t stream) {
+  if (r <= 0) return hipSuccess;
+  if (rmask) {
+    k_filter_rep<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+        rows, r, d, piv, off, min_len, rmask, keys, H, rep);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   k_filter_assign<<<grid_for(H, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
-      g, keys, H, dense, slot_key, slot_region, counters);
+      g, rows, d, piv, keys, H, rmask ? rep : nullptr, dense, slot_key, slot_rep, slot_region,
+      counters);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
-                               int32_t a, int32_t nslots, const unsigned long long* slot_key,
-                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
-                               hipStream_t stream) {
+                               int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
+                               int32_t nslots, const unsigned long long* slot_key,
+                               const int32_t* slot_rep, const int64_t* slot_region,
+                               int32_t* pool, int32_t* fcount, hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
-  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, abits, a, slot_key, slot_region, pool,
-                                                fcount);
+  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, abits, a, rows, piv, rmask, slot_key,
+                                                slot_rep, slot_region, pool, fcount);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_apply(const int32_t* rows, int32_t r, int32_t d, int2* piv,
-                               const int64_t* off, int64_t* len, int32_t min_len,
+                               const int64_t* off, int64_t* len, int32_t min_len, uint32_t rmask,
                                const unsigned long long* keys, uint32_t H, const int32_t* dense,
-                               const int64_t* slot_region, const int32_t* fcount, int64_t* bsum,
-                               hipStream_t stream) {
+                               const int32_t* slot_rep, const int64_t* slot_region,
+                               const int32_t* fcount, int64_t* bsum, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
   const int nb = (int)(((int64_t)r + kPivotTile - 1) / kPivotTile);
-  k_filter_apply<<<nb, kBlock, 0, stream>>>(rows, r, d, piv, off, len, min_len, keys, H, dense,
-                                            slot_region, fcount, bsum);
+  k_filter_apply<<<nb, kBlock, 0, stream>>>(rows, r, d, piv, off, len, min_len, rmask, keys, H,
+                                            dense, slot_rep, slot_region, fcount, bsum);
   return hipGetLastError();
 }
 

@@ -106,7 +106,7 @@ struct Workspace {
   // pivot-list filter: per depth the filtered lists and the rows' new prefix
   // sums; shared by all depths the hash table and slot descriptors
   DevBuf fpool[kMaxK], off2[kMaxK];
-  DevBuf fkeys, fdense, fslot_key, fslot_region, fcount;
+  DevBuf fkeys, frep, fdense, fslot_key, fslot_rep, fslot_region, fcount;
   // per depth: prefix sums of short-row lengths and of long-row tile counts
   DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
   unsigned long long* host = nullptr;  // pinned readback slots
@@ -120,7 +120,8 @@ struct Workspace {
   size_t held() const {
     size_t s = plan.bytes + vbits.bytes + counters.bytes + partials.bytes +
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
-               fkeys.bytes + fdense.bytes + fslot_key.bytes + fslot_region.bytes + fcount.bytes;
+               fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
+               fslot_region.bytes + fcount.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
            off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
@@ -129,7 +130,8 @@ struct Workspace {
   void release_all() {
     plan.release(); vbits.release(); counters.release(); partials.release();
     blkcount.release(); blkprefix.release(); rows2.release(); rows2d.release();
-    fkeys.release(); fdense.release(); fslot_key.release(); fslot_region.release();
+    fkeys.release(); frep.release(); fdense.release(); fslot_key.release(); fslot_rep.release();
+    fslot_region.release();
     fcount.release();
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
@@ -418,16 +420,18 @@ DevPlan build_dev_plan(const hpm_pattern* p, const PatternInfo& P, const std::ve
 
 // ------------------------------------------------------------ matcher
 
+// Device counter slots (and the pinned host slots they are read into).
 enum : int {
-  kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3, kCntSlots = 4,
-  kCntFilterSlots = 5, kCntFilterPool = 6,
-  kHostSplit = 8,   // pinned readback slots 8, 9: short work and long tiles of a split
-  kHostSlots = 16
+  kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3,
+  kCntSlots = 4,        // host slot of read_i64
+  kCntFilterSlots = 8,  // 8..11: groups and pool entries of the two filter tables
+  kHostSplit = 12,      // host slots 12, 13: short work and long tiles of a split
+  kCntNum = 16          // counter slots on the device and in pinned host memory
 };
 
 // Split rows into packed short rows and row-aligned long rows only when a
 // depth has at least this many candidates.
-constexpr int64_t kSplitMinWork = int64_t(1) << 16;
+constexpr int64_t kSplitMinWork = int64_t(1) << 22;
 
 // Pre-filter pivot lists only when a depth has at least this many candidates.
 constexpr int64_t kFilterMinWork = int64_t(1) << 22;
@@ -449,6 +453,7 @@ struct Matcher {
   uint64_t budget = 0;  // scratch limit of the call
   uint64_t limit = 0;   // stop once this many embeddings are found (0 = all)
   bool stopped = false;
+  uint32_t done[kMaxK] = {};  // per depth: relations the pre-filtered lists enforce
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -456,6 +461,27 @@ struct Matcher {
   };
   std::vector<Pending> pending;
   size_t next_event = 0;
+
+  // Scratch this call asked for, per buffer (the largest size), and in total:
+  // the budget bounds this, not the idle buffers the workspace kept from
+  // earlier calls.
+  std::unordered_map<const DevBuf*, size_t> req;
+  uint64_t planned = 0;
+
+  void need(DevBuf& b, size_t want) {
+    size_t& r = req[&b];
+    if (want > r) {
+      planned += want - r;
+      r = want;
+    }
+    b.ensure(want, stream);
+  }
+  // Growth of the call's scratch if it asked b for `want` bytes.
+  uint64_t extra(const DevBuf& b, size_t want) const {
+    const auto it = req.find(&b);
+    const size_t r = it == req.end() ? 0 : it->second;
+    return want > r ? want - r : 0;
+  }
 
   DevPlan* dplan() const { return W->plan.as<DevPlan>(); }
   int64_t bit_words() const { return (G->n + 63) / 64 * 2; }
@@ -536,62 +562,112 @@ struct Matcher {
 
   void ensure_depth(int32_t d, int64_t r_cap) {
     const int64_t nb = (r_cap + hpm::kPivotTile - 1) / hpm::kPivotTile;
-    W->off[d].ensure((size_t)(r_cap + 1) * sizeof(int64_t), stream);
-    W->piv[d].ensure((size_t)std::max<int64_t>(r_cap, 1) * sizeof(int2), stream);
-    W->bsum[d].ensure((size_t)(nb + 1) * sizeof(int64_t), stream);
+    need(W->off[d], (size_t)(r_cap + 1) * sizeof(int64_t));
+    need(W->piv[d], (size_t)std::max<int64_t>(r_cap, 1) * sizeof(int2));
+    need(W->bsum[d], (size_t)(nb + 1) * sizeof(int64_t));
   }
 
   // Point rows whose pivot list has >= kFilterMinLen entries at a filtered copy
-  // of that list (one per distinct list).  On success *offp / *fpool / *work
-  // describe the new candidate ranges; otherwise nothing changes.
+  // of that list, one per group of rows (see launch_filter_keys).  With two or
+  // more positions related to the new one, rows are first grouped by the
+  // images of all of them (the filtered list then holds exactly the
+  // candidates that satisfy every relation with those positions); if those
+  // groups are not shared enough, by pivot list.  On success *offp / *fpool /
+  // *work describe the new candidate ranges and done[d] the relations the
+  // lists enforce; otherwise nothing changes.
   void filter_pivots(int32_t d, const int32_t* rows, int64_t r, int2* piv, const int64_t* off,
                      const int64_t** offp, const int32_t** fpool, int64_t* work) {
     const int64_t max_long = std::min<int64_t>(r, *work / hpm::kFilterMinLen);
     if (max_long == 0) return;
     uint32_t H = 1024;
     while ((int64_t)H < 2 * max_long) H <<= 1;
-    const uint64_t table_bytes = (uint64_t)H * (8 + 4 + 8 + 8);
-    if (W->held() + table_bytes > budget) return;
-    W->fkeys.ensure((size_t)H * 8, stream);
-    W->fdense.ensure((size_t)H * 4, stream);
-    W->fslot_key.ensure((size_t)H * 8, stream);
-    W->fslot_region.ensure((size_t)H * 8, stream);
+    // grouping by all mapped positions would make every row its own group
+    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & ((1u << d) - 1u);
+    const uint32_t rmask =
+        (__builtin_popcount(related) >= 2 && related != (1u << d) - 1u) ? related : 0u;
+    const size_t T = rmask ? 2 : 1;
+    const uint64_t table_bytes =
+        extra(W->fkeys, T * H * 8) + (rmask ? extra(W->frep, (size_t)H * 4) : 0) +
+        extra(W->fdense, (size_t)H * 4) + extra(W->fslot_key, (size_t)H * 8) +
+        (rmask ? extra(W->fslot_rep, (size_t)H * 4) : 0) + extra(W->fslot_region, (size_t)H * 8);
+    if (planned + table_bytes > budget) return;
+    need(W->fkeys, T * H * 8);
+    if (rmask) {
+      need(W->frep, (size_t)H * 4);
+      need(W->fslot_rep, (size_t)H * 4);
+    }
+    need(W->fdense, (size_t)H * 4);
+    need(W->fslot_key, (size_t)H * 8);
+    need(W->fslot_region, (size_t)H * 8);
     auto* keys = W->fkeys.as<unsigned long long>();
-    hip_check(hipMemsetAsync(keys, 0xff, (size_t)H * 8, stream), "memset");
-    hip_check(hipMemsetAsync(counters() + kCntFilterSlots, 0, 2 * sizeof(unsigned long long),
-                             stream),
-              "memset");
+    unsigned long long* cnt = counters() + kCntFilterSlots;
+    hip_check(hipMemsetAsync(keys, 0xff, T * H * 8, stream), "memset");
+    hip_check(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), stream), "memset");
     launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_keys(g, rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, keys,
-                                     H, W->fdense.as<int32_t>(),
-                                     W->fslot_key.as<unsigned long long>(),
-                                     W->fslot_region.as<int64_t>(), counters() + kCntFilterSlots,
-                                     stream);
+      return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, rmask,
+                                       keys, H, cnt + 2, stream);
     });
-    hip_check(hipMemcpyAsync(W->host + kCntFilterSlots, counters() + kCntFilterSlots,
-                             2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+    hip_check(hipMemcpyAsync(W->host + kCntFilterSlots + 2, cnt + 2, 2 * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, stream),
               "readback");
     sync();
-    const int64_t nslots = (int64_t)W->host[kCntFilterSlots];
-    const int64_t pool = (int64_t)W->host[kCntFilterPool];
-    // Filtering reads every distinct list once more; it pays when the lists
-    // are shared, i.e. their total length is well below the depth's work.
-    if (nslots == 0 || pool >= INT32_MAX || 2 * pool > *work) return;
-    const uint64_t more = (uint64_t)pool * 4 + (uint64_t)nslots * 4 + (uint64_t)(r + 1) * 8;
-    if (W->held() + more > budget) return;
-    W->fpool[d].ensure((size_t)std::max<int64_t>(pool, 1) * 4, stream);
-    W->fcount.ensure((size_t)nslots * 4, stream);
-    W->off2[d].ensure((size_t)(r + 1) * 8, stream);
+    const int64_t distinct_related = (int64_t)W->host[kCntFilterSlots + 3];
+    // Number one table's groups; filtering reads every group's list once
+    // more, so it pays when the groups are shared: their total length must be
+    // well below the depth's work.
+    int64_t nslots = 0, pool = 0;
+    auto groups = [&](int t) -> bool {
+      const uint32_t m = t ? rmask : 0u;
+      hip_check(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), stream), "memset");
+      if (t) hip_check(hipMemsetAsync(W->frep.p, 0x7f, (size_t)H * 4, stream), "memset");
+      launch(HPM_K_FILTER, [&] {
+        return hpm::launch_filter_groups(g, rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, m,
+                                         keys + (size_t)t * H, H,
+                                         t ? W->frep.as<int32_t>() : nullptr,
+                                         W->fdense.as<int32_t>(),
+                                         W->fslot_key.as<unsigned long long>(),
+                                         t ? W->fslot_rep.as<int32_t>() : nullptr,
+                                         W->fslot_region.as<int64_t>(), cnt, stream);
+      });
+      hip_check(hipMemcpyAsync(W->host + kCntFilterSlots, cnt, 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, stream),
+                "readback");
+      sync();
+      nslots = (int64_t)W->host[kCntFilterSlots];
+      pool = (int64_t)W->host[kCntFilterSlots + 1];
+      if (nslots > 0 && pool < INT32_MAX && 2 * pool <= *work) return true;
+      nslots = 0;
+      return false;
+    };
+    // Groups by related images give exact lists; they are tried when the
+    // rows share them (at least two rows per group on average).
+    int t_use = -1;
+    if (rmask && 2 * distinct_related <= r && groups(1))
+      t_use = 1;
+    else if (groups(0))
+      t_use = 0;
+    const uint32_t use_mask = t_use == 1 ? rmask : 0u;
+    if (nslots == 0) return;
+    const uint64_t more = extra(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4) +
+                          extra(W->fcount, (size_t)nslots * 4) +
+                          extra(W->off2[d], (size_t)(r + 1) * 8);
+    if (planned + more > budget) return;
+    need(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4);
+    need(W->fcount, (size_t)nslots * 4);
+    need(W->off2[d], (size_t)(r + 1) * 8);
     int64_t* off2 = W->off2[d].as<int64_t>();
     launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_lists(g, dplan(), bits(d), d, (int32_t)nslots,
-                                      W->fslot_key.as<unsigned long long>(),
+      return hpm::launch_filter_lists(g, dplan(), bits(d), d, rows, piv, use_mask,
+                                      (int32_t)nslots, W->fslot_key.as<unsigned long long>(),
+                                      use_mask ? W->fslot_rep.as<int32_t>() : nullptr,
                                       W->fslot_region.as<int64_t>(), W->fpool[d].as<int32_t>(),
                                       W->fcount.as<int32_t>(), stream);
     });
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_apply(rows, (int32_t)r, d, piv, off, off2, hpm::kFilterMinLen,
-                                      keys, H, W->fdense.as<int32_t>(),
+                                      use_mask, keys + (size_t)t_use * H, H,
+                                      W->fdense.as<int32_t>(),
+                                      use_mask ? W->fslot_rep.as<int32_t>() : nullptr,
                                       W->fslot_region.as<int64_t>(), W->fcount.as<int32_t>(),
                                       W->bsum[d].as<int64_t>(), stream);
     });
@@ -600,11 +676,9 @@ struct Matcher {
     *work = read_i64(off2 + r);
     *offp = off2;
     *fpool = W->fpool[d].as<int32_t>();
+    done[d] = use_mask;
     st.filtered_lists += (uint64_t)nslots;
   }
-
-  // Extra bytes ensure(want) would allocate for b.
-  static uint64_t growth(const DevBuf& b, uint64_t want) { return want > b.bytes ? want : 0; }
 
   // Separate rows with at least kAlignMin candidates (row-aligned tiles) from
   // the rest (packed tiles).  On success *S is the short rows' work and *T the
@@ -614,13 +688,13 @@ struct Matcher {
     if (work < kSplitMinWork) return false;
     const uint64_t nb = ((uint64_t)r + hpm::kPivotTile - 1) / hpm::kPivotTile + 1;
     const uint64_t pre = (uint64_t)(r + 1) * sizeof(int64_t);
-    const uint64_t more = growth(W->soff[d], pre) + growth(W->toff[d], pre) +
-                          growth(W->sbsum[d], nb * 8) + growth(W->tbsum[d], nb * 8);
-    if (W->held() + more > budget) return false;
-    W->soff[d].ensure(pre, stream);
-    W->toff[d].ensure(pre, stream);
-    W->sbsum[d].ensure(nb * 8, stream);
-    W->tbsum[d].ensure(nb * 8, stream);
+    const uint64_t more = extra(W->soff[d], pre) + extra(W->toff[d], pre) +
+                          extra(W->sbsum[d], nb * 8) + extra(W->tbsum[d], nb * 8);
+    if (planned + more > budget) return false;
+    need(W->soff[d], pre);
+    need(W->toff[d], pre);
+    need(W->sbsum[d], nb * 8);
+    need(W->tbsum[d], nb * 8);
     int64_t* so = W->soff[d].as<int64_t>();
     int64_t* to = W->toff[d].as<int64_t>();
     launch(HPM_K_PREFIX_SUM, [&] {
@@ -653,6 +727,7 @@ struct Matcher {
     st.raw_work[d] += (uint64_t)work;
     const int64_t* offp = off;
     const int32_t* fpool = nullptr;
+    done[d] = 0;
     if (filter && work >= kFilterMinWork) filter_pivots(d, rows, r, piv, off, &offp, &fpool, &work);
     st.work[d] += (uint64_t)work;
     if (work == 0) return;
@@ -667,13 +742,13 @@ struct Matcher {
       if (g1)
         launch(HPM_K_LAST_LEVEL, [&] {
           return hpm::launch_expand(g, dplan(), bits(d), d, rows, soffp, piv, fpool, (int32_t)r,
-                                    0, S, nullptr, mode, maps, counters() + kCntEmit,
+                                    0, S, nullptr, done[d], mode, maps, counters() + kCntEmit,
                                     maps ? emit_cap() : 0, parts, g1, stream);
         });
       if (g2)
         launch(HPM_K_LAST_LEVEL, [&] {
           return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r,
-                                    0, T, W->toff[d].as<int64_t>(), mode, maps,
+                                    0, T, W->toff[d].as<int64_t>(), done[d], mode, maps,
                                     counters() + kCntEmit, maps ? emit_cap() : 0, parts + g1, g2,
                                     stream);
         });
@@ -688,21 +763,22 @@ struct Matcher {
     if (work <= chunk && split_rows(d, r, offp, work, &S, &T)) {
       // the whole depth in one piece: packed short rows and row-aligned long rows
       st.chunks++;
-      W->rows[d + 1].ensure((size_t)work * (d + 1) * sizeof(int32_t), stream);
+      need(W->rows[d + 1], (size_t)work * (d + 1) * sizeof(int32_t));
       ensure_depth(d + 1, work);
       int32_t* out = W->rows[d + 1].as<int32_t>();
       zero_counter(kCntCursor);
       if (S > 0)
         launch(HPM_K_EXPAND, [&] {
           return hpm::launch_expand(g, dplan(), bits(d), d, rows, W->soff[d].as<int64_t>(), piv,
-                                    fpool, (int32_t)r, 0, S, nullptr, 0, out,
+                                    fpool, (int32_t)r, 0, S, nullptr, done[d], 0, out,
                                     counters() + kCntCursor, (unsigned long long)work,
                                     W->partials.as<unsigned long long>(),
                                     grid_for(S, hpm::kExpandTile), stream);
         });
       launch(HPM_K_EXPAND, [&] {
         return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r, 0,
-                                  T, W->toff[d].as<int64_t>(), 0, out, counters() + kCntCursor,
+                                  T, W->toff[d].as<int64_t>(), done[d], 0, out,
+                                  counters() + kCntCursor,
                                   (unsigned long long)work, W->partials.as<unsigned long long>(),
                                   grid_for(T * hpm::kExpandTile, hpm::kExpandTile), stream);
       });
@@ -716,14 +792,14 @@ struct Matcher {
       const int64_t w1 = std::min(work, w0 + chunk);
       const int64_t n_items = w1 - w0;
       st.chunks++;
-      W->rows[d + 1].ensure((size_t)n_items * (d + 1) * sizeof(int32_t), stream);
+      need(W->rows[d + 1], (size_t)n_items * (d + 1) * sizeof(int32_t));
       ensure_depth(d + 1, n_items);
       int32_t* out = W->rows[d + 1].as<int32_t>();
       zero_counter(kCntCursor);
       const int grid = grid_for(n_items, hpm::kExpandTile);
       launch(HPM_K_EXPAND, [&] {
         return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv,
-                                  fpool, (int32_t)r, w0, w1, nullptr, 0, out,
+                                  fpool, (int32_t)r, w0, w1, nullptr, done[d], 0, out,
                                   counters() + kCntCursor, (unsigned long long)n_items,
                                   W->partials.as<unsigned long long>(), grid, stream);
       });
@@ -762,7 +838,7 @@ struct Matcher {
         c = read_counter(kCntCursor);
       } else {
         const int nb = (int)hpm::edge_scan_blocks(m);
-        W->blkcount.ensure((size_t)nb * sizeof(unsigned long long), stream);
+        need(W->blkcount, (size_t)nb * sizeof(unsigned long long));
         launch(HPM_K_EDGE_SCAN, [&] {
           return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 1, nullptr,
                                        nullptr, 0, W->blkcount.as<unsigned long long>(), nb,
@@ -785,8 +861,8 @@ struct Matcher {
       const int64_t e1 = std::min<int64_t>(m, e0 + cap2);
       st.arcs_scanned = (uint64_t)e1;
       const int grid = (int)hpm::edge_scan_blocks(e1 - e0);
-      W->blkcount.ensure((size_t)(grid + 1) * sizeof(int64_t), stream);
-      W->blkprefix.ensure((size_t)(grid / hpm::kPivotTile + 2) * sizeof(int64_t), stream);
+      need(W->blkcount, (size_t)(grid + 1) * sizeof(int64_t));
+      need(W->blkprefix, (size_t)(grid / hpm::kPivotTile + 2) * sizeof(int64_t));
       int64_t* cnt = W->blkcount.as<int64_t>();
       launch(HPM_K_EDGE_SCAN, [&] {
         return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1, 0,
@@ -801,7 +877,7 @@ struct Matcher {
       if (s2 > e1 - e0) fail(HPM_E_INTERNAL, "scan overflow");
       st.survivors += (uint64_t)s2;
       if (s2 == 0) continue;
-      W->rows2d.ensure((size_t)s2 * 2 * sizeof(int32_t), stream);
+      need(W->rows2d, (size_t)s2 * 2 * sizeof(int32_t));
       ensure_depth(2, s2);
       launch(HPM_K_PREFIX_SUM, [&] {
         return hpm::launch_rows2_gather(W->rows2.as<int32_t>(), cnt, grid, (int32_t)e0,
@@ -1021,10 +1097,31 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       }
     } dg(cur, G->device);
 
+    Workspace* W = own;
+    if (!W) {
+      std::lock_guard<std::mutex> lk(G->mu);
+      if (!G->pool.empty()) {
+        W = G->pool.back();
+        G->pool.pop_back();
+      }
+    }
+    if (!W) W = new Workspace();
+    struct Return {
+      hpm_graph* G;
+      Workspace* W;
+      ~Return() {
+        if (!W) return;
+        std::lock_guard<std::mutex> lk(G->mu);
+        G->pool.push_back(W);
+      }
+    } ret{G, own ? nullptr : W};
+
     if (budget == 0) {
+      // a quarter of the device memory this call could use: what is free
+      // plus what its own workspace already holds
       size_t free_b = 0, total_b = 0;
       hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-      budget = free_b / 4;
+      budget = ((uint64_t)free_b + W->held()) / 4;
     }
 
     // Scratch layout and its budget: the fixed part, then one arc chunk at
@@ -1060,30 +1157,14 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       if (chunk) chunk = std::min<int64_t>(chunk, kFirstKRows);
     }
 
-    Workspace* W = own;
-    if (!W) {
-      std::lock_guard<std::mutex> lk(G->mu);
-      if (!G->pool.empty()) {
-        W = G->pool.back();
-        G->pool.pop_back();
-      }
-    }
-    if (!W) W = new Workspace();
-    struct Return {
-      hpm_graph* G;
-      Workspace* W;
-      ~Return() {
-        if (!W) return;
-        std::lock_guard<std::mutex> lk(G->mu);
-        G->pool.push_back(W);
-      }
-    } ret{G, own ? nullptr : W};
-    if (W->held() > budget) {
+    // The call's own scratch stays within the budget (Matcher::need); idle
+    // buffers kept from earlier calls are dropped once they pass it twice over.
+    if (W->held() > 2 * budget) {
       hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
       W->release_all();
     }
     if (!W->host)
-      hip_check(hipHostMalloc((void**)&W->host, kHostSlots * sizeof(unsigned long long)),
+      hip_check(hipHostMalloc((void**)&W->host, kCntNum * sizeof(unsigned long long)),
                 "hipHostMalloc");
     if (!W->host_plan)
       hip_check(hipHostMalloc((void**)&W->host_plan, sizeof(DevPlan)), "hipHostMalloc");
@@ -1094,20 +1175,21 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     M.chunk = chunk;
     M.budget = budget;
     M.limit = limit;
-    W->plan.ensure(sizeof(DevPlan), stream);
-    W->vbits.ensure((size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t), stream);
-    W->counters.ensure(8 * sizeof(unsigned long long), stream);
-    W->partials.ensure((size_t)max_grid * 2 * sizeof(unsigned long long), stream);
+    M.need(W->plan, sizeof(DevPlan));
+    M.need(W->vbits, (size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t));
+    M.need(W->counters, kCntNum * sizeof(unsigned long long));
+    M.need(W->partials, (size_t)max_grid * 2 * sizeof(unsigned long long));
     if (k >= 3) {
       const int64_t rows2 = std::min<int64_t>(cap2, std::max<int64_t>(G->m, 1));
-      W->rows2.ensure((size_t)rows2 * 2 * sizeof(int32_t), stream);
+      M.need(W->rows2, (size_t)rows2 * 2 * sizeof(int32_t));
     }
     // The plan goes through pinned memory so the copy is truly asynchronous.
     *W->host_plan = plan;
     hip_check(hipMemcpyAsync(W->plan.p, W->host_plan, sizeof(DevPlan), hipMemcpyHostToDevice,
                              stream),
               "plan upload");
-    hip_check(hipMemsetAsync(W->counters.p, 0, 8 * sizeof(unsigned long long), stream), "memset");
+    hip_check(hipMemsetAsync(W->counters.p, 0, kCntNum * sizeof(unsigned long long), stream),
+              "memset");
     M.run();
     M.sync();
     M.st.struct_size = sizeof(hpm_match_stats);
@@ -1358,7 +1440,12 @@ int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
     if (budget == 0) {
       size_t free_b = 0, total_b = 0;
       hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-      budget = free_b / 4;
+      uint64_t pooled = 0;
+      {
+        std::lock_guard<std::mutex> lk(G->mu);
+        for (const Workspace* w : G->pool) pooled += w->held();
+      }
+      budget = ((uint64_t)free_b + pooled) / 4;
     }
     const uint64_t share = budget / (uint64_t)workers;
     // work issued on the caller's stream before the batch comes first
