@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
