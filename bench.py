@@ -217,6 +217,8 @@ def main():
                     help="queries per arrival rate (serve); the first tenth are warm-up")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="1: apply the neighbour-overlap test to depth-2 rows (HPM_F_OVERLAP)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -248,11 +250,13 @@ def main():
     log(f"graph resident: {dg.info()['device_bytes'] / 2**20:.1f} MiB")
     stream = torch.cuda.current_stream()
 
+    extra_flags = hpm.F_OVERLAP if args.overlap else 0
+
     def step(timing):
         counts, stats = [], []
         for p, mode in runs:
             c, _ = hpm.match(dg, p, mode, stream=stream,
-                             flags=hpm.F_TIMING if timing else 0)
+                             flags=(hpm.F_TIMING if timing else 0) | extra_flags)
             counts.append(c)
             stats.append(hpm.last_stats())
         return counts, stats
@@ -401,6 +405,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n": g.n, "m": g.m,
+                   "overlap_test": bool(args.overlap),
                    "queries": ([f"{p.name}/{'iso' if mode == 0 else 'mono'}" for p, mode in runs]
                                if len(runs) <= 16 else f"{len(runs)} patterns"),
                    "matches_per_step": matches_per_step},
@@ -413,6 +418,7 @@ def main():
                        "survivors": st["survivors"], "rows": st["rows"][2:p.k],
                        "work": st["work"][2:p.k], "raw_work": st["raw_work"][2:p.k],
                        "filtered_lists": st["filtered_lists"],
+                       "overlap_removed": st["overlap_removed"],
                        "kernel_ms": {k: round(v, 4) for k, v in st["kernel_ms"].items() if v}}
                       for st, (p, mode) in zip(all_stats[-len(runs):], runs)],
         "roofline": roofline,

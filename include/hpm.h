@@ -129,6 +129,12 @@ typedef struct {
 #define HPM_F_TIMING 0x2u     /* record per-phase device times (hpm_last_stats) */
 #define HPM_F_NO_FILTER 0x4u  /* do not pre-filter long shared candidate lists \
                                  (same result; for checking and measurement) */
+#define HPM_F_OVERLAP 0x8u    /* apply the edge validator's neighbour-overlap  \
+                                 test (Sec. III-B, Alg. 3) to the depth-2 rows: \
+                                 (u,v) is dropped when u and v share fewer      \
+                                 neighbours (either direction) than pattern     \
+                                 positions 0 and 1 do.  Sound, same result;     \
+                                 one more pass over the depth-2 rows. */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(hpm_match_opts); 16 = the layout without
@@ -315,6 +321,7 @@ typedef struct {
   double ms_total;               /* host wall time of the call                        */
   uint64_t filtered_lists;       /* distinct candidate lists pre-filtered             */
   uint64_t raw_work[HPM_MAX_K + 1]; /* candidates per depth before pre-filtering      */
+  uint64_t overlap_removed;      /* depth-2 rows dropped by HPM_F_OVERLAP             */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

@@ -115,6 +115,11 @@ hipError_t launch_rows2_compact(int64_t* blk_count, int32_t nb, int64_t* bsum,
 hipError_t launch_rows2_gather(const int32_t* sparse, const int64_t* prefix, int32_t nb,
                                int32_t e_begin, int32_t e_end, int32_t* dense, int64_t s2,
                                hipStream_t stream);
+// Neighbour-overlap test on n depth-2 rows: the rows whose endpoints share at
+// least `need` neighbours go to out (unspecified order), *cursor += their
+// number (zero it first).
+hipError_t launch_overlap_filter(const DevGraph& g, const int32_t* rows, int64_t n, int32_t need,
+                                 int32_t* out, unsigned long long* cursor, hipStream_t stream);
 // Blocks for an arc scan over `arcs` arcs with out_mode 0 or 1 (one per tile).
 int64_t edge_scan_blocks(int64_t arcs);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]

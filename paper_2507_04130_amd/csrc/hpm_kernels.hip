@@ -553,6 +553,64 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows2(const int2* __restrict_
   for (int64_t i = threadIdx.x; i < n; i += kBlock) dense[lo + i] = src[i];
 }
 
+// ------------------------------------------------------------ neighbour overlap
+//
+// The edge validator's neighbour-overlap test (Sec. III-B, Alg. 3): in any
+// embedding the images of the common neighbours of pattern positions 0 and 1
+// are distinct common neighbours of their images, so a depth-2 row (u, v)
+// whose u and v share fewer neighbours (either direction, u and v excluded)
+// than positions 0 and 1 share in the pattern (need) extends to nothing.  One
+// lane per row walks the neighbours of the endpoint with the smaller degree
+// and stops as soon as `need` common neighbours are found; the rows that pass
+// are written to out (one atomic per wavefront).
+__device__ __forceinline__ bool adjacent_either(const DevGraph& g, int32_t y, int32_t w) {
+  return find_in(g.out_nbrs, g.out_off[y], g.out_off[y + 1], w) >= 0 ||
+         find_in(g.in_nbrs, g.in_off[y], g.in_off[y + 1], w) >= 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_overlap_filter(DevGraph g, const int2* __restrict__ rows,
+                                                           int64_t n, int32_t need,
+                                                           int2* __restrict__ out,
+                                                           unsigned long long* __restrict__ cursor) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t base = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 64; base < n;
+       base += nwaves * 64) {
+    const int64_t i = base + lane;
+    bool keep = false;
+    int2 rw = make_int2(0, 0);
+    if (i < n) {
+      rw = rows[i];
+      int32_t x = rw.x, y = rw.y;
+      const int32_t dx = (g.out_off[x + 1] - g.out_off[x]) + (g.in_off[x + 1] - g.in_off[x]);
+      const int32_t dy = (g.out_off[y + 1] - g.out_off[y]) + (g.in_off[y + 1] - g.in_off[y]);
+      if (dy < dx) {
+        const int32_t t = x;
+        x = y;
+        y = t;
+      }
+      int32_t cnt = 0;
+      for (int32_t j = g.out_off[x]; j < g.out_off[x + 1] && cnt < need; ++j) {
+        const int32_t w = g.out_nbrs[j];
+        if (w != y && adjacent_either(g, y, w)) ++cnt;
+      }
+      for (int32_t j = g.in_off[x]; j < g.in_off[x + 1] && cnt < need; ++j) {
+        const int32_t w = g.in_nbrs[j];
+        // a reciprocal neighbour was already counted from the out-list
+        if (w != y && find_in(g.out_nbrs, g.out_off[x], g.out_off[x + 1], w) < 0 &&
+            adjacent_either(g, y, w))
+          ++cnt;
+      }
+      keep = cnt >= need;
+    }
+    const uint64_t m = __ballot(keep);
+    unsigned long long slot0 = 0;
+    if (lane == 0 && m) slot0 = atomicAdd(cursor, (unsigned long long)__popcll(m));
+    slot0 = __shfl(slot0, 0);
+    if (keep) out[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = rw;
+  }
+}
+
 // ------------------------------------------------------------ extension
 
 __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan* __restrict__ P,
@@ -1527,6 +1585,15 @@ hipError_t launch_rows2_compact(int64_t* blk_count, int32_t nb, int64_t* bsum,
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_scan_lengths(blk_count, nb, bsum, stream);
+}
+
+hipError_t launch_overlap_filter(const DevGraph& g, const int32_t* rows, int64_t n, int32_t need,
+                                 int32_t* out, unsigned long long* cursor, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int grid = grid_for((n + 63) / 64, kWaves, kMaxGridSimple);
+  k_overlap_filter<<<grid, kBlock, 0, stream>>>(g, reinterpret_cast<const int2*>(rows), n, need,
+                                                reinterpret_cast<int2*>(out), cursor);
+  return hipGetLastError();
 }
 
 hipError_t launch_rows2_gather(const int32_t* sparse, const int64_t* prefix, int32_t nb,

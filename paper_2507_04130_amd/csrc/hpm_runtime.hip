@@ -454,6 +454,7 @@ struct Matcher {
   uint64_t limit = 0;   // stop once this many embeddings are found (0 = all)
   bool stopped = false;
   uint32_t done[kMaxK] = {};  // per depth: relations the pre-filtered lists enforce
+  int32_t overlap_need = 0;   // common neighbours of positions 0 and 1 (overlap test on)
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -883,7 +884,21 @@ struct Matcher {
         return hpm::launch_rows2_gather(W->rows2.as<int32_t>(), cnt, grid, (int32_t)e0,
                                         (int32_t)e1, W->rows2d.as<int32_t>(), s2, stream);
       });
-      process_depth(2, W->rows2d.as<int32_t>(), s2);
+      if (overlap_need > 0) {
+        // the sparse scan regions are free again: the rows that pass go there
+        zero_counter(kCntCursor);
+        launch(HPM_K_EDGE_SCAN, [&] {
+          return hpm::launch_overlap_filter(g, W->rows2d.as<int32_t>(), s2, overlap_need,
+                                            W->rows2.as<int32_t>(), counters() + kCntCursor,
+                                            stream);
+        });
+        const int64_t kept = (int64_t)read_counter(kCntCursor);
+        if (kept > s2) fail(HPM_E_INTERNAL, "overlap filter overflow");
+        st.overlap_removed += (uint64_t)(s2 - kept);
+        process_depth(2, W->rows2.as<int32_t>(), kept);
+      } else {
+        process_depth(2, W->rows2d.as<int32_t>(), s2);
+      }
       check_limit();
     }
     st.count = read_total();
@@ -1175,6 +1190,14 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     M.chunk = chunk;
     M.budget = budget;
     M.limit = limit;
+    if ((flags & HPM_F_OVERLAP) && k >= 3) {
+      // pattern vertices adjacent (either direction) to both of the first two
+      const int32_t u = order[0], v = order[1];
+      for (int32_t w = 0; w < k; ++w)
+        if (w != u && w != v && (info.adj[(size_t)u * k + w] || info.adj[(size_t)w * k + u]) &&
+            (info.adj[(size_t)v * k + w] || info.adj[(size_t)w * k + v]))
+          M.overlap_need++;
+    }
     M.need(W->plan, sizeof(DevPlan));
     M.need(W->vbits, (size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t));
     M.need(W->counters, kCntNum * sizeof(unsigned long long));

@@ -22,6 +22,7 @@ ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
+F_OVERLAP = 0x8
 MAX_K = 16
 KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand", "last_level",
            "reduce", "filter")
@@ -58,7 +59,8 @@ class _Stats(ctypes.Structure):
                 ("chunks", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
                 ("kernel_launches", ctypes.c_uint64 * len(KERNELS)),
                 ("kernel_ms", ctypes.c_double * len(KERNELS)), ("ms_total", ctypes.c_double),
-                ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1))]
+                ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1)),
+                ("overlap_removed", ctypes.c_uint64)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -363,6 +365,7 @@ def last_stats() -> dict:
         "kernel_launches": dict(zip(KERNELS, list(s.kernel_launches))),
         "kernel_ms": dict(zip(KERNELS, list(s.kernel_ms))), "ms_total": s.ms_total,
         "filtered_lists": s.filtered_lists, "raw_work": list(s.raw_work),
+        "overlap_removed": s.overlap_removed,
     }
 
 

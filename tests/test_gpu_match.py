@@ -374,3 +374,26 @@ def test_first_k_stops_early_with_valid_rows():
     counts, _ = hpm.match_batch(dbig, [motif("cycle3")] * 3, [MONO, ISO, MONO], workers=2,
                                 max_matches=5)
     assert counts == [min(5, hpm.match(dbig, motif("cycle3"), m)[0]) for m in (MONO, ISO, MONO)]
+
+
+def test_overlap_test_changes_nothing():
+    # HPM_F_OVERLAP drops depth-2 rows whose endpoints share fewer neighbours
+    # than the pattern's first two positions; results must not change, and rows
+    # must be dropped where those positions have common neighbours.
+    g = rmat(10, 1 << 13, seed=51)
+    dg = hpm.Graph.from_host(g)
+    removed = 0
+    for name in ("clique4_minus1", "ffl_tail", "cycle4", "star3_back", "cycle3"):
+        for mode in (ISO, MONO):
+            p = motif(name)
+            c0, _ = hpm.match(dg, p, mode)
+            c1, _ = hpm.match(dg, p, mode, flags=hpm.F_OVERLAP)
+            removed += hpm.last_stats()["overlap_removed"]
+            assert c0 == c1, (name, mode)
+            if c1 <= 1_000_000:
+                _, r0 = gpu_rows(dg, p, mode)
+                _, r1 = gpu_rows(dg, p, mode, flags=hpm.F_OVERLAP)
+                np.testing.assert_array_equal(r0, r1)
+            assert c1 == oracle.match(g, p, mode, threads=8, rows=False).count
+    say(f"overlap test removed {removed} depth-2 rows")
+    assert removed > 0
