@@ -109,3 +109,32 @@ def test_connectome_query(connectome, qi):
         assert_distinct(rows)
     c8, _ = hpm.match(dg, p, MONO, budget=8 << 30)
     assert c8 == cnt
+
+
+def test_served_pool_full_size(connectome):
+    # every query of the served workload's pool, in the mix on a server with
+    # the benchmark's settings, gives the oracle's stored count; queries with
+    # at most 10^6 embeddings also return mapping rows whose fingerprint is
+    # the oracle's
+    import torch
+    g, dg = connectome
+    pool = configs.c5_pool()
+    say(f"served pool: {len(pool)} queries")
+    srv = hpm.Server(dg, workers=8, budget=64 << 30)
+    tickets = []
+    for p, mode, cnt, fp in pool:
+        buf = None
+        if 0 < cnt <= 1_000_000:
+            buf = torch.empty((cnt, p.k), dtype=torch.int32, device="cuda")
+        tickets.append(srv.submit(p, mode, mappings=buf))
+    checked = 0
+    for t, (p, mode, cnt, fp) in zip(tickets, pool):
+        r = srv.poll(t, wait=True)
+        assert r["status"] == 0 and r["count"] == cnt, (p.name, r, cnt)
+        if "rows" in r and cnt > 0:
+            rows = r["rows"].cpu().numpy()
+            assert oracle.fingerprint(rows) == fp, p.name
+            checked += 1
+    srv.close()
+    say(f"  {checked} mapping sets checked by fingerprint")
+    assert checked > 10

@@ -64,3 +64,20 @@ def test_rmat20_query(rmat20, qi):
     np.testing.assert_array_equal(lexsorted(mine), sl.rows)
     del rows_dev
     torch.cuda.empty_cache()
+
+
+def test_batched_workload_full_size(rmat20):
+    # the 256 screened random patterns in one batched call (8 workers, as the
+    # benchmark times it) give the oracle's stored counts, pattern by pattern
+    g, dg = rmat20
+    runs = configs.c4_patterns()
+    want = configs.c4_expected_counts(len(runs))
+    say(f"batched workload: {len(runs)} patterns")
+    counts, status = hpm.match_batch(dg, [p for p, _ in runs], [m for _, m in runs], workers=8)
+    assert status == [0] * len(runs)
+    bad = [i for i, (a, b) in enumerate(zip(counts, want)) if a != b]
+    assert not bad, f"patterns {bad[:8]} differ from the oracle"
+    # first-k over the same patterns: min(count, 1000) each
+    capped, _ = hpm.match_batch(dg, [p for p, _ in runs[:64]], [m for _, m in runs[:64]],
+                                workers=8, max_matches=1000)
+    assert capped == [min(c, 1000) for c in want[:64]]
