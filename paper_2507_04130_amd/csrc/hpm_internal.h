@@ -26,6 +26,7 @@ constexpr int kFilterMinLen = 32;     // pivot lists at least this long are pre-
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 constexpr int kAlignMin = 512;        // rows with this many candidates get tiles of their own
 constexpr int kMarkEntries = 4 * kExpandTile;  // longest list window marked into a tile
+constexpr uint32_t kDonePivot = 1u << 31;  // filtered rows: the pivot position's relations done
 
 // Graph as the kernels see it.  m < 2^31, so offsets and arc ids are int32.
 struct DevGraph {
@@ -137,7 +138,8 @@ hipError_t launch_scan_lengths(int64_t* off, int32_t r, int64_t* bsum, hipStream
 // off.  toff non-NULL: w_end tiles of long rows (toff = their tile prefix sums
 // from launch_split_rows, off = the full length prefix sums).
 // done: positions whose relations with position d the pre-filtered lists
-// already enforce (rows with pivot code bit 1 skip them).
+// already enforce (rows with pivot code bit 1 skip them); kDonePivot stands
+// for each row's own pivot position.
 hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t* abits, int32_t d,
                          const int32_t* rows, const int64_t* off, const int2* piv,
                          const int32_t* fpool, int32_t r, int64_t w_begin, int64_t w_end,

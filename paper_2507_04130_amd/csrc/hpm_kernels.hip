@@ -705,6 +705,13 @@ __device__ __forceinline__ int32_t pack_cons(int q, int dir, int req) {
   return q | (dir << 5) | (req << 6);
 }
 
+// Positions whose relations with the new one a pre-filtered list already
+// enforces: the mask of a grouping by related images, or (kDonePivot) the
+// row's own pivot position b for a grouping by pivot list.
+__device__ __forceinline__ uint32_t done_mask(uint32_t done, int32_t b) {
+  return (done & ~kDonePivot) | ((done & kDonePivot) ? (1u << b) : 0u);
+}
+
 // A single-row tile whose candidate ids lie in [cmin, cmax] checks relations
 // through an LDS bitmap when that range fits in the tile pool.
 __device__ __forceinline__ bool tile_bitmap(int32_t cmin, int32_t cmax) {
@@ -806,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
       const int2 pv = piv[r_lo];
       const int32_t b = pv.x >> 2;
       const bool vo = (pv.x & 1) != 0;
-      const uint32_t skip = (pv.x & 2) ? done : 0u;
+      const uint32_t skip = (pv.x & 2) ? done_mask(done, b) : 0u;
       int32_t n = 0;
       for (int q = 0; q < d; ++q) {
         if ((skip >> q) & 1u) continue;
@@ -925,7 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
         if (same_row) {
           const int32_t b0 = __shfl(b, 0);
           const bool vo0 = __shfl((int)via_out, 0) != 0;
-          const uint32_t skip0 = __shfl((int)filtered, 0) ? done : 0u;
+          const uint32_t skip0 = __shfl((int)filtered, 0) ? done_mask(done, b0) : 0u;
           const int32_t cmin = __shfl(c, 0);
           const int32_t cmax = __shfl(c, 63 - __clzll((long long)vmask));
           for (int q = 0; q < d; ++q) {
@@ -946,7 +953,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(
             }
           }
         } else {
-          const uint32_t skip = filtered ? done : 0u;
+          const uint32_t skip = filtered ? done_mask(done, b) : 0u;
           for (int q = 0; q < d && ok; ++q) {
             if ((skip >> q) & 1u) continue;
             const int32_t fq = rowv(q);
@@ -1256,8 +1263,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
 
 // One block per group: order-preserving compaction of the candidates of the
 // representative row's pivot list that pass the vertex validator of position
-// a, the pivot-arc predicate and (rmask != 0) every condition between a and
-// the positions in rmask.  The list is taken kExpandTile entries at a time
+// a, the pivot-arc predicate and every other condition between a and the
+// positions in rmask (rmask == 0: the pivot position alone).  The list is taken kExpandTile entries at a time
 // (4 consecutive ones per thread); every checked list is cut once per piece
 // to the piece's id range, staged in LDS when short enough and searched
 // there, else searched in the cut range.
@@ -1293,12 +1300,14 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
   const bool iso = P->mode == 0;
   const int lane = threadIdx.x & 63;
   if (rmask && threadIdx.x < d) s_f[threadIdx.x] = rows[i * d + threadIdx.x];
+  if (!rmask && threadIdx.x == 0) s_f[b] = pv_v;
+  // relations checked here: every condition with a position in rmask (with
+  // the pivot position alone for pivot-list groups) but the pivot arc itself
+  const uint32_t cmask = rmask ? rmask : (1u << b);
   if (threadIdx.x == 0) {
-    // relations checked here: every condition with a position in rmask but
-    // the pivot arc itself
     int32_t n = 0;
     for (int q = 0; q < d; ++q) {
-      if (!((rmask >> q) & 1u)) continue;
+      if (!((cmask >> q) & 1u)) continue;
       const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
       if (arc_in ? !(q == b && out_dir) : iso) s_cons[n++] = pack_cons(q, 0, arc_in);
       if (arc_out ? !(q == b && !out_dir) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);

@@ -677,7 +677,7 @@ struct Matcher {
     *work = read_i64(off2 + r);
     *offp = off2;
     *fpool = W->fpool[d].as<int32_t>();
-    done[d] = use_mask;
+    done[d] = use_mask ? use_mask : hpm::kDonePivot;
     st.filtered_lists += (uint64_t)nslots;
   }
 
