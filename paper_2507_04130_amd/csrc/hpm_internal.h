@@ -24,6 +24,7 @@ constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront sta
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
 constexpr int kFilterMinLen = 32;     // pivot lists at least this long are pre-filtered
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
+constexpr int kValidatorSpan = 256;   // consecutive vertices a wavefront validates per step
 constexpr int kAlignMin = 512;        // rows with this many candidates get tiles of their own
 constexpr int kMarkEntries = 4 * kExpandTile;  // longest list window marked into a tile
 constexpr uint32_t kDonePivot = 1u << 31;  // filtered rows: the pivot position's relations done

@@ -290,6 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_columns_in_order(const int32_t* __re
 
 // ------------------------------------------------------------ vertex validator
 
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
                                                              const DevPlan* __restrict__ P,
                                                              uint32_t* __restrict__ vbits,
@@ -300,41 +302,72 @@ __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
   // same test is a sound filter for every later position, so it is computed
   // once per vertex.  One bit per vertex keeps each position's flags small
   // enough (n/8 bytes) to stay in L2 while kernels test random vertices.
+  // Each wavefront takes 256 consecutive vertices per step, four per lane, so
+  // every array is read with 16-byte loads; a lane's four flag bits per
+  // position are merged across 8 lanes into one 32-bit bitmap word.
   const int32_t k = P->k;
   uint32_t cols = 0;
   for (int p = 0; p < k; ++p) cols |= P->vmask[p];
   const int lane = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
-       base += (int64_t)gridDim.x * kBlock) {
-    const int64_t v = base + lane;
-    uint32_t f = 0;
-    if (v < g.n) {
-      const int32_t dout = g.out_off[v + 1] - g.out_off[v];
-      const int32_t din = g.in_off[v + 1] - g.in_off[v];
-      int32_t x[kMaxCols];
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int64_t n = g.n;
+  for (int64_t base = wave * kValidatorSpan; base < n; base += nwaves * kValidatorSpan) {
+    const int64_t v0 = base + 4 * lane;
+    int32_t oo[5], io[5], x[kMaxCols][4];
+    if (v0 + 4 <= n) {
+      const v4i a = *reinterpret_cast<const v4i*>(g.out_off + v0);
+      const v4i c = *reinterpret_cast<const v4i*>(g.in_off + v0);
+      oo[0] = a.x; oo[1] = a.y; oo[2] = a.z; oo[3] = a.w; oo[4] = g.out_off[v0 + 4];
+      io[0] = c.x; io[1] = c.y; io[2] = c.z; io[3] = c.w; io[4] = g.in_off[v0 + 4];
 #pragma unroll
-      for (int c = 0; c < kMaxCols; ++c) x[c] = ((cols >> c) & 1u) ? g.vcol[c][v] : 0;
-      for (int p = 0; p < k; ++p) {
-        bool ok = din >= P->pin[p] && dout >= P->pout[p];
-        const uint32_t mask = P->vmask[p];
+      for (int col = 0; col < kMaxCols; ++col) {
+        v4i w = {0, 0, 0, 0};
+        if ((cols >> col) & 1u) w = *reinterpret_cast<const v4i*>(g.vcol[col] + v0);
+        x[col][0] = w.x; x[col][1] = w.y; x[col][2] = w.z; x[col][3] = w.w;
+      }
+    } else {
 #pragma unroll
-        for (int c = 0; c < kMaxCols; ++c)
-          if ((mask >> c) & 1u) ok = ok && x[c] >= P->vlo[p][c] && x[c] <= P->vhi[p][c];
-        f |= (uint32_t)ok << p;
+      for (int j = 0; j < 5; ++j) {
+        const bool in = v0 + j <= n;
+        oo[j] = in ? g.out_off[v0 + j] : 0;
+        io[j] = in ? g.in_off[v0 + j] : 0;
+      }
+#pragma unroll
+      for (int col = 0; col < kMaxCols; ++col)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          x[col][j] = (v0 + j < n && ((cols >> col) & 1u)) ? g.vcol[col][v0 + j] : 0;
+    }
+    uint32_t f[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f[j] = 0;
+      if (v0 + j < n) {
+        const int32_t dout = oo[j + 1] - oo[j], din = io[j + 1] - io[j];
+        for (int p = 0; p < k; ++p) {
+          bool ok = din >= P->pin[p] && dout >= P->pout[p];
+          const uint32_t mask = P->vmask[p];
+#pragma unroll
+          for (int col = 0; col < kMaxCols; ++col)
+            if ((mask >> col) & 1u) ok = ok && x[col][j] >= P->vlo[p][col] && x[col][j] <= P->vhi[p][col];
+          f[j] |= (uint32_t)ok << p;
+        }
       }
     }
     for (int p = 0; p < k; ++p) {
-      const uint64_t bp = __ballot(((f >> p) & 1u) != 0);
-      if (lane == 0) {  // base is a multiple of 64: two whole words
-        uint32_t* w = vbits + p * words + (base >> 5);
-        w[0] = (uint32_t)bp;
-        w[1] = (uint32_t)(bp >> 32);
-      }
+      // this lane's 4 bits at (lane % 8) * 4, OR-merged over the 8 lanes of a word
+      uint32_t w = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w |= ((f[j] >> p) & 1u) << ((lane & 7) * 4 + j);
+      w |= __shfl_xor(w, 1);
+      w |= __shfl_xor(w, 2);
+      w |= __shfl_xor(w, 4);
+      if ((lane & 7) == 0 && v0 < n) vbits[p * words + ((base + 4 * lane) >> 5)] = w;
     }
   }
 }
 
-typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool test_bit(const uint32_t* __restrict__ bits, int32_t v) {
   return ((bits[v >> 5] >> (v & 31)) & 1u) != 0;
@@ -1187,19 +1220,26 @@ __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restr
                                                           uint32_t H,
                                                           unsigned long long* __restrict__ distinct) {
   const int ntab = rmask ? 2 : 1;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
-       i += (int64_t)gridDim.x * kBlock) {
-    if (off[i + 1] - off[i] < min_len) continue;
+  const int lane = threadIdx.x & 63;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < r; i0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ins = i < r && off[i + 1] - off[i] >= min_len;
     for (int t = 0; t < ntab; ++t) {
-      unsigned long long* tab = keys + (size_t)t * H;
-      const unsigned long long key = row_key(rows, i, d, piv[i].x, t ? rmask : 0u);
-      uint32_t h = key_hash(key) & (H - 1);
-      while (true) {  // H exceeds the number of rows, so a free slot exists
-        const unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
-        if (prev == kEmptyKey) atomicAdd(&distinct[t], 1ull);
-        if (prev == kEmptyKey || prev == key) break;
-        h = (h + 1) & (H - 1);
+      bool fresh = false;
+      if (ins) {
+        unsigned long long* tab = keys + (size_t)t * H;
+        const unsigned long long key = row_key(rows, i, d, piv[i].x, t ? rmask : 0u);
+        uint32_t h = key_hash(key) & (H - 1);
+        while (true) {  // H exceeds the number of rows, so a free slot exists
+          const unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
+          if (prev == kEmptyKey) fresh = true;
+          if (prev == kEmptyKey || prev == key) break;
+          h = (h + 1) & (H - 1);
+        }
       }
+      // one atomic per wavefront for the new keys it inserted
+      const uint64_t m = __ballot(fresh);
+      if (lane == 0 && m) atomicAdd(&distinct[t], (unsigned long long)__popcll(m));
     }
   }
 }
@@ -1237,27 +1277,46 @@ __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
                                                           int32_t* __restrict__ slot_rep,
                                                           int64_t* __restrict__ slot_region,
                                                           unsigned long long* __restrict__ counters) {
-  for (int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x; h < H;
-       h += (int64_t)gridDim.x * kBlock) {
-    const unsigned long long key = keys[h];
-    if (key == kEmptyKey) continue;
-    int32_t v, code;
-    if (rep) {
-      const int32_t i = rep[h];
-      code = piv[i].x;
-      v = rows[(int64_t)i * d + (code >> 2)];
-    } else {
-      v = (int32_t)(key & 0xffffffffull);
-      code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+  // kBlock slots per block and step; group ids and pool offsets are ranked
+  // within the block and reserved with one atomic per counter and step.
+  __shared__ unsigned long long s_scan[kWaves + 1];
+  __shared__ unsigned long long s_base[2];
+  for (int64_t h0 = (int64_t)blockIdx.x * kBlock; h0 < H; h0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t h = h0 + threadIdx.x;
+    unsigned long long key = kEmptyKey;
+    if (h < H) key = keys[h];
+    const bool occ = key != kEmptyKey;
+    int32_t L = 0;
+    if (occ) {
+      int32_t v, code;
+      if (rep) {
+        const int32_t i = rep[h];
+        code = piv[i].x;
+        v = rows[(int64_t)i * d + (code >> 2)];
+      } else {
+        v = (int32_t)(key & 0xffffffffull);
+        code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+      }
+      L = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
     }
-    const int32_t L = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
-    const unsigned long long s = atomicAdd(&counters[0], 1ull);
-    dense[h] = (int32_t)s;
-    if (rep)
-      slot_rep[s] = rep[h];
-    else
-      slot_key[s] = key;
-    slot_region[s] = (int64_t)atomicAdd(&counters[1], (unsigned long long)L);
+    unsigned long long nocc, nlen;
+    const unsigned long long ex_s = block_exclusive_scan<unsigned long long>(occ ? 1ull : 0ull, s_scan, &nocc);
+    const unsigned long long ex_p = block_exclusive_scan<unsigned long long>((unsigned long long)L, s_scan, &nlen);
+    if (threadIdx.x == 0) {
+      s_base[0] = nocc ? atomicAdd(&counters[0], nocc) : 0ull;
+      s_base[1] = nlen ? atomicAdd(&counters[1], nlen) : 0ull;
+    }
+    __syncthreads();
+    if (occ) {
+      const unsigned long long sidx = s_base[0] + ex_s;
+      dense[h] = (int32_t)sidx;
+      if (rep)
+        slot_rep[sidx] = rep[h];
+      else
+        slot_key[sidx] = key;
+      slot_region[sidx] = (int64_t)(s_base[1] + ex_p);
+    }
+    __syncthreads();  // s_base is rewritten by the next step
   }
 }
 
@@ -1557,8 +1616,9 @@ hipError_t launch_columns_in_order(const int32_t* col, const int32_t* in_eid, in
 hipError_t launch_vertex_validator(const DevGraph& g, const DevPlan* plan, uint32_t* vbits,
                                    int64_t words, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
-  k_vertex_validator<<<grid_for(g.n, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(g, plan, vbits,
-                                                                                   words);
+  k_vertex_validator<<<grid_for((g.n + kValidatorSpan - 1) / kValidatorSpan, kWaves,
+                                kMaxGridSimple),
+                       kBlock, 0, stream>>>(g, plan, vbits, words);
   return hipGetLastError();
 }
 
