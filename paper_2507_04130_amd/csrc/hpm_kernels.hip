@@ -339,27 +339,26 @@ __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
         for (int j = 0; j < 4; ++j)
           x[col][j] = (v0 + j < n && ((cols >> col) & 1u)) ? g.vcol[col][v0 + j] : 0;
     }
-    uint32_t f[4];
+    int32_t dout[4], din[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      f[j] = 0;
-      if (v0 + j < n) {
-        const int32_t dout = oo[j + 1] - oo[j], din = io[j + 1] - io[j];
-        for (int p = 0; p < k; ++p) {
-          bool ok = din >= P->pin[p] && dout >= P->pout[p];
-          const uint32_t mask = P->vmask[p];
-#pragma unroll
-          for (int col = 0; col < kMaxCols; ++col)
-            if ((mask >> col) & 1u) ok = ok && x[col][j] >= P->vlo[p][col] && x[col][j] <= P->vhi[p][col];
-          f[j] |= (uint32_t)ok << p;
-        }
-      }
+      dout[j] = oo[j + 1] - oo[j];
+      din[j] = io[j + 1] - io[j];
     }
     for (int p = 0; p < k; ++p) {
-      // this lane's 4 bits at (lane % 8) * 4, OR-merged over the 8 lanes of a word
+      // the position's plan entries once per step, then this lane's 4 bits at
+      // (lane % 8) * 4, OR-merged over the 8 lanes of a bitmap word
+      const int32_t pin = P->pin[p], pout = P->pout[p];
+      const uint32_t mask = P->vmask[p];
       uint32_t w = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) w |= ((f[j] >> p) & 1u) << ((lane & 7) * 4 + j);
+      for (int j = 0; j < 4; ++j) {
+        bool ok = v0 + j < n && din[j] >= pin && dout[j] >= pout;
+#pragma unroll
+        for (int col = 0; col < kMaxCols; ++col)
+          if ((mask >> col) & 1u) ok = ok && x[col][j] >= P->vlo[p][col] && x[col][j] <= P->vhi[p][col];
+        w |= (uint32_t)ok << ((lane & 7) * 4 + j);
+      }
       w |= __shfl_xor(w, 1);
       w |= __shfl_xor(w, 2);
       w |= __shfl_xor(w, 4);
@@ -367,7 +366,6 @@ __global__ __launch_bounds__(kBlock) void k_vertex_validator(DevGraph g,
     }
   }
 }
-
 
 __device__ __forceinline__ bool test_bit(const uint32_t* __restrict__ bits, int32_t v) {
   return ((bits[v >> 5] >> (v & 31)) & 1u) != 0;
