@@ -268,7 +268,8 @@ def main():
     extra = {}
     if batch:
         # one batched call per step; per-kernel times come from one sequential
-        # step with HIP events, which is also the one-at-a-time comparison
+        # step with HIP events, the one-at-a-time comparison from another
+        # without them
         from synth import configs
         expected = configs.c4_expected_counts(len(runs))
         seq_counts, all_stats = [], []
@@ -280,9 +281,15 @@ def main():
             all_stats.append(hpm.last_stats())
             if i % 32 == 31:
                 log(f"sequential: {i + 1} queries, {time.perf_counter() - t_seq:.3f}s")
-        seq_s = time.perf_counter() - t_seq
         bad = [i for i, (a, b) in enumerate(zip(seq_counts, expected)) if a != b]
         assert not bad, f"counts differ from the oracle's for patterns {bad[:8]}"
+        # the one-at-a-time comparison, without the per-kernel events
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter()
+        for p, mode in runs:
+            hpm.match(dg, p, mode, stream=stream)
+        torch.cuda.synchronize()
+        seq_s = time.perf_counter() - t_seq
         log(f"sequential step {seq_s:.3f}s; all {len(runs)} counts equal the oracle's")
         for i in range(args.warmup):
             hpm.match_batch(dg, pats, modes, workers=args.batch_workers, stream=stream)
