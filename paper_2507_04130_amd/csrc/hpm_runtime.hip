@@ -608,11 +608,14 @@ struct Matcher {
       return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, rmask,
                                        keys, H, cnt + 2, stream);
     });
-    hip_check(hipMemcpyAsync(W->host + kCntFilterSlots + 2, cnt + 2, 2 * sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, stream),
-              "readback");
-    sync();
-    const int64_t distinct_related = (int64_t)W->host[kCntFilterSlots + 3];
+    int64_t distinct_related = 0;
+    if (rmask) {
+      hip_check(hipMemcpyAsync(W->host + kCntFilterSlots + 2, cnt + 2,
+                               2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+                "readback");
+      sync();
+      distinct_related = (int64_t)W->host[kCntFilterSlots + 3];
+    }
     // Number one table's groups; filtering reads every group's list once
     // more, so it pays when the groups are shared: their total length must be
     // well below the depth's work.
