@@ -154,14 +154,15 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
 hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64_t* toff,
                              int64_t* sbsum, int64_t* tbsum, hipStream_t stream);
 // Pivot-list filter.  off: the rows' exclusive length prefix sums.  Rows with
-// a list of >= min_len entries are grouped by key: table 0 by pivot list and,
-// when rmask != 0, table 1 by the images of the positions in rmask (every
-// position related to the new one).  Each table has H slots (a power of two
-// above the number of such rows), table t at keys + t * H; keys must hold ~0
-// (empty) on entry.  distinct[t] += keys of table t.
+// a list of >= min_len entries are grouped by key: table 0 by pivot list;
+// tables 1 and 2 (when mask1 / mask2 != 0) by the images of the positions in
+// that mask, which must contain every position tied to the new one by a
+// pattern arc (so equal keys give equal pivots).  Each table has H slots (a
+// power of two above the number of such rows), table t at keys + t * H; keys
+// must hold ~0 (empty) on entry.  distinct[t] += keys of table t.
 hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
-                                const int64_t* off, int32_t min_len, uint32_t rmask,
-                                unsigned long long* keys, uint32_t H,
+                                const int64_t* off, int32_t min_len, uint32_t mask1,
+                                uint32_t mask2, unsigned long long* keys, uint32_t H,
                                 unsigned long long* distinct, hipStream_t stream);
 // Number the groups of one table (keys[H]; rmask 0 for table 0, else the
 // table-1 mask with rep[H] holding INT32_MAX on entry): dense[H] maps slots to

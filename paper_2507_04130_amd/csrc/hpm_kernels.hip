@@ -1206,27 +1206,29 @@ __device__ __forceinline__ uint32_t table_find(const unsigned long long* __restr
 }
 
 // off: exclusive prefix sums of the rows' list lengths (off[r] = total).
-// Table 0 (keys[0..H)) groups by pivot list; with rmask != 0 table 1
-// (keys[H..2H)) groups by the images of the positions in rmask.
+// Table 0 (keys[0..H)) groups by pivot list; table t = 1, 2 (keys[t*H ..)),
+// when masks[t-1] != 0, groups by the images of the positions in that mask.
 // distinct[t] counts the keys of table t.
 __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restrict__ rows,
                                                           int32_t r, int32_t d,
                                                           const int2* __restrict__ piv,
                                                           const int64_t* __restrict__ off,
-                                                          int32_t min_len, uint32_t rmask,
+                                                          int32_t min_len, uint32_t mask1,
+                                                          uint32_t mask2,
                                                           unsigned long long* __restrict__ keys,
                                                           uint32_t H,
                                                           unsigned long long* __restrict__ distinct) {
-  const int ntab = rmask ? 2 : 1;
   const int lane = threadIdx.x & 63;
   for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < r; i0 += (int64_t)gridDim.x * kBlock) {
     const int64_t i = i0 + threadIdx.x;
     const bool ins = i < r && off[i + 1] - off[i] >= min_len;
-    for (int t = 0; t < ntab; ++t) {
+    for (int t = 0; t < 3; ++t) {
+      const uint32_t m = t == 0 ? 0u : (t == 1 ? mask1 : mask2);
+      if (t > 0 && m == 0) continue;  // uniform
       bool fresh = false;
       if (ins) {
         unsigned long long* tab = keys + (size_t)t * H;
-        const unsigned long long key = row_key(rows, i, d, piv[i].x, t ? rmask : 0u);
+        const unsigned long long key = row_key(rows, i, d, piv[i].x, m);
         uint32_t h = key_hash(key) & (H - 1);
         while (true) {  // H exceeds the number of rows, so a free slot exists
           const unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
@@ -1236,8 +1238,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restr
         }
       }
       // one atomic per wavefront for the new keys it inserted
-      const uint64_t m = __ballot(fresh);
-      if (lane == 0 && m) atomicAdd(&distinct[t], (unsigned long long)__popcll(m));
+      const uint64_t bm = __ballot(fresh);
+      if (lane == 0 && bm) atomicAdd(&distinct[t], (unsigned long long)__popcll(bm));
     }
   }
 }
@@ -1734,12 +1736,12 @@ hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64
 }
 
 hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
-                                const int64_t* off, int32_t min_len, uint32_t rmask,
-                                unsigned long long* keys, uint32_t H,
+                                const int64_t* off, int32_t min_len, uint32_t mask1,
+                                uint32_t mask2, unsigned long long* keys, uint32_t H,
                                 unsigned long long* distinct, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
   k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
-      rows, r, d, piv, off, min_len, rmask, keys, H, distinct);
+      rows, r, d, piv, off, min_len, mask1, mask2, keys, H, distinct);
   return hipGetLastError();
 }
 

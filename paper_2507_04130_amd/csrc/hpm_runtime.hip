@@ -424,8 +424,8 @@ DevPlan build_dev_plan(const hpm_pattern* p, const PatternInfo& P, const std::ve
 enum : int {
   kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3,
   kCntSlots = 4,        // host slot of read_i64
-  kCntFilterSlots = 8,  // 8..11: groups and pool entries of the two filter tables
-  kHostSplit = 12,      // host slots 12, 13: short work and long tiles of a split
+  kCntFilterSlots = 8,  // 8, 9: groups and pool entries; 10..12: keys of the filter tables
+  kHostSplit = 14,      // host slots 14, 15: short work and long tiles of a split
   kCntNum = 16          // counter slots on the device and in pinned host memory
 };
 
@@ -582,18 +582,28 @@ struct Matcher {
     if (max_long == 0) return;
     uint32_t H = 1024;
     while ((int64_t)H < 2 * max_long) H <<= 1;
-    // grouping by all mapped positions would make every row its own group
-    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & ((1u << d) - 1u);
-    const uint32_t rmask =
-        (__builtin_popcount(related) >= 2 && related != (1u << d) - 1u) ? related : 0u;
-    const size_t T = rmask ? 2 : 1;
+    // Candidate keys besides the pivot list: the positions tied to the new one
+    // by a pattern arc (table 1) and, for induced isomorphism, those plus every
+    // earlier position but the last (table 2: the filter then also enforces
+    // their non-arcs).  A key of all mapped positions would make every row
+    // its own group.
+    const uint32_t all = (1u << d) - 1u;
+    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & all;
+    uint32_t masks[3] = {0u, 0u, 0u};
+    if (__builtin_popcount(related) >= 2 && related != all) masks[1] = related;
+    if (host_plan.mode == HPM_ISO && d >= 3) {
+      const uint32_t wide = related | ((1u << (d - 1)) - 1u);
+      if (wide != all && wide != related) masks[2] = wide;
+    }
+    const size_t T = masks[2] ? 3 : (masks[1] ? 2 : 1);
+    const bool grouped = masks[1] || masks[2];
     const uint64_t table_bytes =
-        extra(W->fkeys, T * H * 8) + (rmask ? extra(W->frep, (size_t)H * 4) : 0) +
+        extra(W->fkeys, T * H * 8) + (grouped ? extra(W->frep, (size_t)H * 4) : 0) +
         extra(W->fdense, (size_t)H * 4) + extra(W->fslot_key, (size_t)H * 8) +
-        (rmask ? extra(W->fslot_rep, (size_t)H * 4) : 0) + extra(W->fslot_region, (size_t)H * 8);
+        (grouped ? extra(W->fslot_rep, (size_t)H * 4) : 0) + extra(W->fslot_region, (size_t)H * 8);
     if (planned + table_bytes > budget) return;
     need(W->fkeys, T * H * 8);
-    if (rmask) {
+    if (grouped) {
       need(W->frep, (size_t)H * 4);
       need(W->fslot_rep, (size_t)H * 4);
     }
@@ -603,25 +613,25 @@ struct Matcher {
     auto* keys = W->fkeys.as<unsigned long long>();
     unsigned long long* cnt = counters() + kCntFilterSlots;
     hip_check(hipMemsetAsync(keys, 0xff, T * H * 8, stream), "memset");
-    hip_check(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), stream), "memset");
+    hip_check(hipMemsetAsync(cnt, 0, 5 * sizeof(unsigned long long), stream), "memset");
     launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen, rmask,
-                                       keys, H, cnt + 2, stream);
+      return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen,
+                                       masks[1], masks[2], keys, H, cnt + 2, stream);
     });
-    int64_t distinct_related = 0;
-    if (rmask) {
+    int64_t distinct[3] = {0, 0, 0};
+    if (grouped) {
       hip_check(hipMemcpyAsync(W->host + kCntFilterSlots + 2, cnt + 2,
-                               2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+                               3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
                 "readback");
       sync();
-      distinct_related = (int64_t)W->host[kCntFilterSlots + 3];
+      for (int t = 0; t < 3; ++t) distinct[t] = (int64_t)W->host[kCntFilterSlots + 2 + t];
     }
     // Number one table's groups; filtering reads every group's list once
     // more, so it pays when the groups are shared: their total length must be
     // well below the depth's work.
     int64_t nslots = 0, pool = 0;
     auto groups = [&](int t) -> bool {
-      const uint32_t m = t ? rmask : 0u;
+      const uint32_t m = masks[t];
       hip_check(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), stream), "memset");
       if (t) hip_check(hipMemsetAsync(W->frep.p, 0x7f, (size_t)H * 4, stream), "memset");
       launch(HPM_K_FILTER, [&] {
@@ -643,14 +653,13 @@ struct Matcher {
       nslots = 0;
       return false;
     };
-    // Groups by related images give exact lists; they are tried when the
-    // rows share them (at least two rows per group on average).
+    // Wider keys enforce more and are tried first when rows share them (at
+    // least two rows per group on average).
     int t_use = -1;
-    if (rmask && 2 * distinct_related <= r && groups(1))
-      t_use = 1;
-    else if (groups(0))
-      t_use = 0;
-    const uint32_t use_mask = t_use == 1 ? rmask : 0u;
+    for (int t = 2; t >= 1 && t_use < 0; --t)
+      if (masks[t] && 2 * distinct[t] <= r && groups(t)) t_use = t;
+    if (t_use < 0 && groups(0)) t_use = 0;
+    const uint32_t use_mask = t_use > 0 ? masks[t_use] : 0u;
     if (nslots == 0) return;
     const uint64_t more = extra(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4) +
                           extra(W->fcount, (size_t)nslots * 4) +
