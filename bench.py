@@ -32,7 +32,9 @@ HBM_PEAK_GBS = 8000.0
 #   arc scan          12 B per arc (tail, head, arc label) + 8 B per surviving row
 #   extension         20 B per candidate (candidate id 4, label 4, arc label 4,
 #                     in/out degree 8) + 4(d+1) B per written row
-#   last level        20 B per candidate + 4k B per written mapping
+#   last level        20 B per candidate + 4k B per written mapping; a row
+#                     counted from its filtered list's length moves its row,
+#                     offsets and pivot (4d + 24 B) plus 4 B per list probe
 B_VERTEX, B_ARC, B_ROW2, B_CAND = 13, 12, 8, 20
 
 
@@ -87,7 +89,9 @@ def kernel_bytes(stats_list, g, runs):
         for d in range(2, k - 1):
             out["expand"] += B_CAND * st["work"][d] + 4 * (d + 1) * st["rows"][d + 1]
         if k >= 3:
-            out["last_level"] += B_CAND * st["work"][k - 1]
+            d = k - 1
+            out["last_level"] += (B_CAND * (st["work"][d] - st["counted_work"]) +
+                                  (4 * d + 24 + 4 * d) * st["counted_rows"])
     return out
 
 

@@ -322,6 +322,8 @@ typedef struct {
   uint64_t filtered_lists;       /* distinct candidate lists pre-filtered             */
   uint64_t raw_work[HPM_MAX_K + 1]; /* candidates per depth before pre-filtering      */
   uint64_t overlap_removed;      /* depth-2 rows dropped by HPM_F_OVERLAP             */
+  uint64_t counted_rows;         /* last-level rows counted from their filtered list's */
+  uint64_t counted_work;         /* length (and the candidates those lists hold)       */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

@@ -147,6 +147,13 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
                          const int64_t* toff, uint32_t done, int out_mode, int32_t* out,
                          unsigned long long* cursor, unsigned long long out_cap,
                          unsigned long long* partials, int grid, hipStream_t stream);
+// Last-level count of r rows whose filtered lists leave only injectivity to
+// check (filtered rows: list length minus the row's images found in the list;
+// other rows: every candidate checked); per-block sums into partials[grid].
+hipError_t launch_count_rows(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
+                             int32_t d, const int32_t* rows, const int64_t* off, const int2* piv,
+                             const int32_t* fpool, int32_t r, unsigned long long* partials,
+                             int grid, hipStream_t stream);
 // Split rows by list length (prefix sums off[0..r]): soff[0..r] = prefix sums
 // of the lengths of rows shorter than kAlignMin (long rows count 0), toff[0..r]
 // = prefix sums of the tile counts of long rows; sbsum/tbsum as for

@@ -1111,6 +1111,81 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   }
 }
 
+// Last level, count only, after a filter that left no relation to check on
+// filtered rows (monomorphism, every arc-related position enforced): such a
+// row's embeddings are its filtered list minus the row's own images found in
+// it (injectivity), so it costs d binary searches instead of one item per
+// candidate.  Rows left unfiltered (short lists, or a group-key collision)
+// check their candidates one by one.  One lane per row; per-block sums go to
+// partials[blockIdx].
+__global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan* __restrict__ P,
+                                                       const uint32_t* __restrict__ abits,
+                                                       int32_t d, const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ off,
+                                                       const int2* __restrict__ piv,
+                                                       const int32_t* __restrict__ fpool,
+                                                       int32_t r,
+                                                       unsigned long long* __restrict__ partials) {
+  __shared__ unsigned long long s_scan[kWaves + 1];
+  const int32_t a = d;
+  const uint32_t fw = P->fwd[a], bw = P->bwd[a];
+  const bool iso = P->mode == 0;
+  unsigned long long my_count = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
+       i += (int64_t)gridDim.x * kBlock) {
+    const int64_t o = off[i];
+    const int32_t len = (int32_t)(off[i + 1] - o);
+    if (len == 0) continue;
+    const int2 pv = piv[i];
+    const int32_t b = pv.x >> 2;
+    const bool via_out = (pv.x & 1) != 0;
+    const int32_t* row = rows + i * d;
+    if (pv.x & 2) {
+      int32_t cnt = len;
+      for (int q = 0; q < d; ++q)
+        if (find_in(fpool, pv.y, pv.y + len, row[q]) >= 0) --cnt;
+      my_count += (unsigned long long)cnt;
+      continue;
+    }
+    for (int32_t j = 0; j < len; ++j) {
+      const int32_t pos = pv.y + j;
+      const int32_t c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
+      bool ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
+      if (ok) {
+        if (via_out) {
+          if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
+        } else if (P->amask[a][b]) {
+          ok = arc_ok_in(g, P, a, b, pos);
+        }
+      }
+      for (int q = 0; q < d && ok; ++q) ok = row[q] != c;
+      for (int q = 0; q < d && ok; ++q) {
+        const int32_t fq = row[q];
+        if ((fw >> q) & 1u) {
+          if (!(q == b && via_out)) {
+            const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
+            ok = e >= 0 && arc_ok(g, P, q, a, e);
+          }
+        } else if (iso) {
+          ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
+        }
+        if (!ok) break;
+        if ((bw >> q) & 1u) {
+          if (!(q == b && !via_out)) {
+            const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
+            ok = e >= 0 && arc_ok_in(g, P, a, q, e);
+          }
+        } else if (iso) {
+          ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
+        }
+      }
+      my_count += ok ? 1ull : 0ull;
+    }
+  }
+  const unsigned long long tot = block_sum<unsigned long long>(my_count, s_scan);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 // Rows with at least kAlignMin candidates get tiles of their own: soff[i] is
 // the length of a shorter row (0 for a long one), toff[i] the tile count of a
 // long row (0 for a short one); per-block sums go to sbsum / tbsum for
@@ -1720,6 +1795,15 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
       break;
   }
 #undef HPM_EXPAND
+  return hipGetLastError();
+}
+
+hipError_t launch_count_rows(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
+                             int32_t d, const int32_t* rows, const int64_t* off, const int2* piv,
+                             const int32_t* fpool, int32_t r, unsigned long long* partials,
+                             int grid, hipStream_t stream) {
+  if (r <= 0) return hipSuccess;
+  k_count_rows<<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r, partials);
   return hipGetLastError();
 }
 

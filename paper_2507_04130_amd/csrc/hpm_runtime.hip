@@ -693,6 +693,15 @@ struct Matcher {
     st.filtered_lists += (uint64_t)nslots;
   }
 
+  // Monomorphism, filter applied at depth d and every arc-related position
+  // enforced by the filtered lists (so a filtered row only needs injectivity).
+  bool counts_by_rows(int32_t d) const {
+    if (host_plan.mode == HPM_ISO || done[d] == 0) return false;
+    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & ((1u << d) - 1u);
+    if (done[d] == hpm::kDonePivot) return __builtin_popcount(related) == 1;
+    return (related & ~done[d]) == 0;
+  }
+
   // Separate rows with at least kAlignMin candidates (row-aligned tiles) from
   // the rest (packed tiles).  On success *S is the short rows' work and *T the
   // long rows' tile count (W->soff[d] / W->toff[d] hold the prefix sums).
@@ -744,6 +753,24 @@ struct Matcher {
     if (filter && work >= kFilterMinWork) filter_pivots(d, rows, r, piv, off, &offp, &fpool, &work);
     st.work[d] += (uint64_t)work;
     if (work == 0) return;
+    if (d == k - 1 && !maps && counts_by_rows(d)) {
+      // every condition is in the filtered lists: each row's count follows
+      // from its list length and its own images
+      const int grid = grid_for(r, hpm::kBlock);
+      unsigned long long* parts = W->partials.as<unsigned long long>();
+      st.counted_rows += (uint64_t)r;
+      st.counted_work += (uint64_t)work;
+      launch(HPM_K_LAST_LEVEL, [&] {
+        return hpm::launch_count_rows(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r,
+                                      parts, grid, stream);
+      });
+      launch(HPM_K_REDUCE, [&] {
+        return hpm::launch_reduce_counts(parts, grid, counters() + kCntTotal,
+                                         reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
+                                         stream);
+      });
+      return;
+    }
     if (d == k - 1) {
       int64_t S = work, T = 0;
       const bool split = split_rows(d, r, offp, work, &S, &T);
