@@ -35,6 +35,9 @@ HBM_PEAK_GBS = 8000.0
 #   last level        20 B per candidate + 4k B per written mapping; a row
 #                     counted from its filtered list's length moves its row,
 #                     offsets and pivot (4d + 24 B) plus 4 B per list probe
+#   filter            per grouped row its images, pivot and offsets twice
+#                     (insert, redirect: 2 x 24 B + 8d B); per list entry of a
+#                     group 8 B (entry, kept copy)
 B_VERTEX, B_ARC, B_ROW2, B_CAND = 13, 12, 8, 20
 
 
@@ -81,7 +84,7 @@ def workload(name):
 
 def kernel_bytes(stats_list, g, runs):
     """Algorithmic bytes per kernel family, summed over the given match calls."""
-    out = {"vertex_validator": 0, "edge_scan": 0, "expand": 0, "last_level": 0}
+    out = {"vertex_validator": 0, "edge_scan": 0, "expand": 0, "last_level": 0, "filter": 0}
     for st, (p, _) in zip(stats_list, runs):
         k = p.k
         out["vertex_validator"] += B_VERTEX * g.n
@@ -92,6 +95,9 @@ def kernel_bytes(stats_list, g, runs):
             d = k - 1
             out["last_level"] += (B_CAND * (st["work"][d] - st["counted_work"]) +
                                   (4 * d + 24 + 4 * d) * st["counted_rows"])
+        # the filtered depths are not recorded per depth: take the deepest
+        # row width as an upper bound of the images per row
+        out["filter"] += (48 + 8 * (k - 1)) * st["filter_rows"] + 8 * st["filter_entries"]
     return out
 
 
@@ -101,13 +107,14 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
-    each scaled by the same counter on a 1 GiB device copy), or None when the
-    summary is missing or was taken on a different kernel source."""
+def measured_traffic(workload, kernel, launches_per_step):
+    """HBM bytes per launch of kernel family `kernel` from the committed counter
+    summary (profiles/<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE summed
+    over the family's dispatches in one step, each scaled by the same counter
+    on a 1 GiB device copy), divided by the family's launches per step; None
+    when the summary is missing or was taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or not launches_per_step:
         return None
     fields = {}
     for line in open(path):
@@ -115,7 +122,8 @@ def measured_traffic(workload, kernel):
             fields = dict(kv.split("=", 1) for kv in line.split())
     if not fields or fields.get("source_sha256") != kernel_source_sha():
         return None
-    return int(float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"]))
+    step = float(fields["fetch_bytes_per_step"]) + float(fields["write_bytes_per_step"])
+    return int(step / launches_per_step)
 
 
 def cpu_baseline(g, runs, seconds_target):
@@ -405,7 +413,7 @@ def main():
     achieved = bytes_by[dom] / (fam_ms[dom] / 1000.0) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, dom),
+                "traffic": measured_traffic(args.workload, dom, launches / timed_steps),
                 "kernel": dom, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(bytes_by[dom] / launches)}
     scan_gbs = bytes_by["edge_scan"] / (scan_ms / 1000.0) / 1e9 if scan_ms > 0 else None

@@ -324,6 +324,8 @@ typedef struct {
   uint64_t overlap_removed;      /* depth-2 rows dropped by HPM_F_OVERLAP             */
   uint64_t counted_rows;         /* last-level rows counted from their filtered list's */
   uint64_t counted_work;         /* length (and the candidates those lists hold)       */
+  uint64_t filter_rows;          /* rows of the depths whose lists were pre-filtered   */
+  uint64_t filter_entries;       /* list entries the pre-filter read (all its groups)  */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

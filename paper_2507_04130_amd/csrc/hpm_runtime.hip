@@ -691,6 +691,8 @@ struct Matcher {
     *fpool = W->fpool[d].as<int32_t>();
     done[d] = use_mask ? use_mask : hpm::kDonePivot;
     st.filtered_lists += (uint64_t)nslots;
+    st.filter_rows += (uint64_t)r;
+    st.filter_entries += (uint64_t)pool;
   }
 
   // Monomorphism, filter applied at depth d and every arc-related position

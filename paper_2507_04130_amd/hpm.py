@@ -61,7 +61,8 @@ class _Stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * len(KERNELS)), ("ms_total", ctypes.c_double),
                 ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1)),
                 ("overlap_removed", ctypes.c_uint64), ("counted_rows", ctypes.c_uint64),
-                ("counted_work", ctypes.c_uint64)]
+                ("counted_work", ctypes.c_uint64), ("filter_rows", ctypes.c_uint64),
+                ("filter_entries", ctypes.c_uint64)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -368,6 +369,7 @@ def last_stats() -> dict:
         "filtered_lists": s.filtered_lists, "raw_work": list(s.raw_work),
         "overlap_removed": s.overlap_removed,
         "counted_rows": s.counted_rows, "counted_work": s.counted_work,
+        "filter_rows": s.filter_rows, "filter_entries": s.filter_entries,
     }
 
 
