@@ -120,7 +120,8 @@ def measured_traffic(workload, kernel, launches_per_step):
     for line in open(path):
         if line.startswith(f"kernel={kernel} "):
             fields = dict(kv.split("=", 1) for kv in line.split())
-    if not fields or fields.get("source_sha256") != kernel_source_sha():
+    if (not fields or fields.get("source_sha256") != kernel_source_sha() or
+            "fetch_bytes_per_step" not in fields or "write_bytes_per_step" not in fields):
         return None
     step = float(fields["fetch_bytes_per_step"]) + float(fields["write_bytes_per_step"])
     return int(step / launches_per_step)
