@@ -222,8 +222,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat20",
                     choices=["rmat20", "er1k", "chunglu", "batch256", "serve"])
-    ap.add_argument("--batch-workers", type=int, default=4,
-                    help="host threads / streams of the batched call (batch256)")
+    ap.add_argument("--batch-workers", type=int, default=0,
+                    help="host threads / streams of the batched call (batch256); 0 = tuned")
     ap.add_argument("--qps", default="100,500,1000,2000",
                     help="arrival rates of the serve workload (comma separated)")
     ap.add_argument("--serve-queries", type=int, default=400,
@@ -304,6 +304,10 @@ def main():
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t_seq
         log(f"sequential step {seq_s:.3f}s; all {len(runs)} counts equal the oracle's")
+        tuned_ms = None
+        if args.batch_workers == 0:
+            args.batch_workers, tuned_ms = hpm.batch_tune(dg, pats, modes, stream=stream)
+            log(f"tuned: {args.batch_workers} workers ({tuned_ms:.1f} ms per batch)")
         for i in range(args.warmup):
             hpm.match_batch(dg, pats, modes, workers=args.batch_workers, stream=stream)
             torch.cuda.synchronize()
@@ -316,7 +320,7 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         assert counts == expected, "batched counts differ from the oracle's"
-        extra = {"batch_workers": args.batch_workers,
+        extra = {"batch_workers": args.batch_workers, "tuned_ms_per_batch": tuned_ms,
                  "queries_per_sec": len(runs) * args.steps / elapsed,
                  "sequential_queries_per_sec": len(runs) / seq_s,
                  "sequential_ms_per_step": 1000.0 * seq_s,

@@ -201,6 +201,21 @@ int hpm_match_batch(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
                     int32_t workers, uint64_t* counts, int32_t* status);
 
 /*
+ * hpm_batch_tune -- pick the worker count for hpm_match_batch on this batch.
+ *
+ * Runs the batch once to warm every worker's scratch, then once with each of
+ * 1, 2, 4, 8, 16 and 32 workers (each run checked to give the same counts),
+ * and returns in *best_workers the fastest count (host wall time; in *best_ms
+ * that time when best_ms is not NULL).  The batched form runs independent
+ * queries on concurrent streams, so its best width depends on the query mix
+ * and the graph.  Errors: as for hpm_match_batch; HPM_E_ARG for an empty
+ * batch.
+ */
+int hpm_batch_tune(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
+                   const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                   int32_t* best_workers, double* best_ms);
+
+/*
  * Serving: a resident graph answering a stream of queries.
  *
  * A server owns `workers` host threads, each driving its own non-blocking HIP

@@ -6,5 +6,5 @@ thin ctypes binding.
 """
 from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_FILTER, F_NO_REORDER, F_OVERLAP, F_TIMING, Graph,  # noqa: F401
                   HpmError, Server,
-                  abi_version, last_stats, load, match, match_batch, plan_order,
+                  abi_version, batch_tune, last_stats, load, match, match_batch, plan_order,
                   status_string)

@@ -1549,6 +1549,38 @@ int hpm_match_batch(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
   });
 }
 
+int hpm_batch_tune(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
+                   const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                   int32_t* best_workers, double* best_ms) {
+  return guarded([&]() -> int {
+    if (!best_workers) fail(HPM_E_ARG, "best_workers is NULL");
+    if (n <= 0) fail(HPM_E_ARG, "empty batch");
+    std::vector<uint64_t> counts((size_t)n), first((size_t)n);
+    std::vector<int32_t> status((size_t)n);
+    // one untimed pass grows every worker's scratch to its working size
+    int st = hpm_match_batch(gc, n, patterns, modes, stream, opts, 16, first.data(), status.data());
+    if (st != HPM_OK) return st;
+    static const int32_t kCandidates[] = {1, 2, 4, 8, 16, 32};
+    double best = -1.0;
+    int32_t arg = 0;
+    for (int32_t w : kCandidates) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = hpm_match_batch(gc, n, patterns, modes, stream, opts, w, counts.data(), status.data());
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (st != HPM_OK) return st;
+      if (counts != first) fail(HPM_E_INTERNAL, "batch counts differ between worker counts");
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        arg = w;
+      }
+    }
+    *best_workers = arg;
+    if (best_ms) *best_ms = best;
+    return HPM_OK;
+  });
+}
+
 int hpm_server_create(hpm_server** out, const hpm_graph* gc, const hpm_server_opts* opts) {
   return guarded([&]() -> int {
     if (!out) fail(HPM_E_ARG, "out is NULL");

@@ -29,6 +29,7 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match", "hpm_match_batch",
+           "hpm_batch_tune",
            "hpm_server_create", "hpm_server_submit", "hpm_server_poll", "hpm_server_read_stats",
            "hpm_server_destroy", "hpm_plan_order", "hpm_last_stats", "hpm_status_string",
            "hpm_last_error", "hpm_abi_version")
@@ -113,6 +114,8 @@ def load() -> ctypes.CDLL:
                               ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
     lib.hpm_match_batch.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
                                     I32, P, P]
+    lib.hpm_batch_tune.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
+                                   ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
     lib.hpm_server_create.argtypes = [ctypes.POINTER(P), P, ctypes.POINTER(_ServerOpts)]
     lib.hpm_server_submit.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P, U64,
                                       ctypes.POINTER(U64)]
@@ -126,7 +129,7 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-                 "hpm_match_batch", "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
+                 "hpm_match_batch", "hpm_batch_tune", "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
                  "hpm_server_read_stats", "hpm_server_destroy", "hpm_plan_order",
                  "hpm_last_stats"):
         getattr(lib, name).restype = ctypes.c_int
@@ -290,6 +293,28 @@ def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
     _check(lib.hpm_match_batch(g.handle, n, structs, _ptr(md), _stream_handle(stream),
                                ctypes.byref(opts), int(workers), _ptr(counts), _ptr(status)))
     return [int(c) for c in counts[:n]], [int(x) for x in status[:n]]
+
+
+def batch_tune(g: Graph, patterns, modes, stream=None, budget: int | None = None,
+               flags: int = 0, max_matches: int = 0):
+    """Fastest worker count for match_batch on this batch (hpm_batch_tune):
+    returns (workers, milliseconds)."""
+    lib = load()
+    n = len(patterns)
+    for p in patterns:
+        _check_columns(g, p)
+    structs = (_Pattern * max(n, 1))()
+    keep = []
+    for i, p in enumerate(patterns):
+        st, arrs = _pattern_struct(p)
+        structs[i] = st
+        keep.append(arrs)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), int(max_matches))
+    w, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib.hpm_batch_tune(g.handle, n, structs, _ptr(md), _stream_handle(stream),
+                              ctypes.byref(opts), ctypes.byref(w), ctypes.byref(ms)))
+    return int(w.value), float(ms.value)
 
 
 class Server:

@@ -336,6 +336,10 @@ def test_batch_equals_single_and_oracle():
             assert c == hpm.match(dg, p, m)[0]
     for p, m, c in zip(pats[:16], modes[:16], counts[:16]):
         assert c == oracle.match(g, p, m, threads=8, rows=False).count
+    # the worker-count tuner runs every width on the same batch (checking the
+    # counts agree) and returns one of them
+    w, ms = hpm.batch_tune(dg, pats, modes)
+    assert w in (1, 2, 4, 8, 16, 32) and ms > 0
     # a failing pattern reports its own status and the others still run
     bad = make_pattern(4, [(0, 1), (2, 3)], 1, 1)
     with pytest.raises(hpm.HpmError):

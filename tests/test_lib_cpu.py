@@ -190,6 +190,7 @@ def test_server_entry_points_reject_null_arguments():
     assert lib.hpm_server_read_stats(None, ctypes.byref(s)) == hb.E_ARG
     assert lib.hpm_server_destroy(None) == hb.OK
     assert lib.hpm_match_batch(None, 0, None, None, None, None, 0, None, None) == hb.E_ARG
+    assert lib.hpm_batch_tune(None, 1, None, None, None, None, None, None) == hb.E_ARG
 
 
 def test_motif_orders_are_valid():
