@@ -341,6 +341,8 @@ typedef struct {
   uint64_t counted_work;         /* length (and the candidates those lists hold)       */
   uint64_t filter_rows;          /* rows of the depths whose lists were pre-filtered   */
   uint64_t filter_entries;       /* list entries the pre-filter read (all its groups)  */
+  uint64_t filter_pieces;        /* blocks its list pass ran: one per group, more for  */
+                                 /* lists longer than one piece of 1024 entries         */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

@@ -23,6 +23,10 @@ constexpr int kTilePool = 2048;       // LDS entries for staged adjacency lists 
 constexpr int kWaveList = kTilePool / kWaves;  // longest list one wavefront stages
 constexpr int kMaxCons = 2 * kMaxK;   // checked relations of one new position
 constexpr int kFilterMinLen = 32;     // pivot lists at least this long are pre-filtered
+constexpr int kFilterPiece = kExpandTile;  // list entries per block of the filter
+constexpr int kAssignItems = 16;     // hash slots per thread and step when numbering groups
+constexpr int kAssignTile = kBlock * kAssignItems;
+constexpr int kMergePieces = 64;     // filter pieces per block when closing the gaps
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 constexpr int kValidatorSpan = 256;   // consecutive vertices a wavefront validates per step
 constexpr int kAlignMin = 512;        // rows with this many candidates get tiles of their own
@@ -182,13 +186,27 @@ hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t 
                                 int32_t* rep, int32_t* dense, unsigned long long* slot_key,
                                 int32_t* slot_rep, int64_t* slot_region,
                                 unsigned long long* counters, hipStream_t stream);
-// One block per group: the filtered list into pool + slot_region[s], its
-// length into fcount[s].
+// Pieces per group (raw list length split into runs of plen entries):
+// pbase[0..nslots] = their exclusive prefix sums, pbase[nslots] = total;
+// bsum as for launch_scan_lengths; pslot[piece] = its group (total entries).
+hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t d,
+                                const int2* piv, int32_t nslots,
+                                const unsigned long long* slot_key, const int32_t* slot_rep,
+                                int32_t plen, int64_t* pbase, int64_t* bsum, int32_t* pslot,
+                                hipStream_t stream);
+// One block per piece (grid >= pbase[nslots]; the blocks past it exit): the
+// filtered list of each group into pool + slot_region[s], its length into
+// fcount[s].  Groups of two or more pieces go through tmp (pool's size) and
+// a second kernel that closes the gaps; tmp may be NULL only when every group
+// is one piece.  pcnt / pslot hold grid entries (pslot from
+// launch_filter_pieces).
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                                int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
-                               int32_t nslots, const unsigned long long* slot_key,
-                               const int32_t* slot_rep, const int64_t* slot_region,
-                               int32_t* pool, int32_t* fcount, hipStream_t stream);
+                               int32_t nslots, const int64_t* pbase, int32_t plen, int32_t grid,
+                               const unsigned long long* slot_key, const int32_t* slot_rep,
+                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
+                               int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
+                               hipStream_t stream);
 // New list lengths into len[0..r) (+ block sums), grouped rows redirected in
 // piv (code bit 1); a row whose images differ from its group's representative
 // stays as it is.

@@ -1352,79 +1352,150 @@ __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
                                                           int32_t* __restrict__ slot_rep,
                                                           int64_t* __restrict__ slot_region,
                                                           unsigned long long* __restrict__ counters) {
-  // kBlock slots per block and step; group ids and pool offsets are ranked
-  // within the block and reserved with one atomic per counter and step.
+  // kAssignTile slots per block and step (thread t owns slots t, t + kBlock,
+  // ...); group ids and pool offsets are ranked within the block and
+  // reserved with one atomic per counter and step.
   __shared__ unsigned long long s_scan[kWaves + 1];
   __shared__ unsigned long long s_base[2];
-  for (int64_t h0 = (int64_t)blockIdx.x * kBlock; h0 < H; h0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t h = h0 + threadIdx.x;
-    unsigned long long key = kEmptyKey;
-    if (h < H) key = keys[h];
-    const bool occ = key != kEmptyKey;
-    int32_t L = 0;
-    if (occ) {
-      int32_t v, code;
-      if (rep) {
-        const int32_t i = rep[h];
-        code = piv[i].x;
-        v = rows[(int64_t)i * d + (code >> 2)];
-      } else {
-        v = (int32_t)(key & 0xffffffffull);
-        code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+  for (int64_t h0 = (int64_t)blockIdx.x * kAssignTile; h0 < H;
+       h0 += (int64_t)gridDim.x * kAssignTile) {
+    uint32_t occ = 0;
+    int32_t L[kAssignItems];
+    unsigned long long lmine = 0;
+#pragma unroll
+    for (int j = 0; j < kAssignItems; ++j) {
+      L[j] = 0;
+      const int64_t h = h0 + j * kBlock + threadIdx.x;
+      const unsigned long long key = h < H ? keys[h] : kEmptyKey;
+      if (key != kEmptyKey) {
+        int32_t v, code;
+        if (rep) {
+          const int32_t i = rep[h];
+          code = piv[i].x;
+          v = rows[(int64_t)i * d + (code >> 2)];
+        } else {
+          v = (int32_t)(key & 0xffffffffull);
+          code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+        }
+        L[j] = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
+        occ |= 1u << j;
+        lmine += (unsigned long long)L[j];
       }
-      L = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
     }
     unsigned long long nocc, nlen;
-    const unsigned long long ex_s = block_exclusive_scan<unsigned long long>(occ ? 1ull : 0ull, s_scan, &nocc);
-    const unsigned long long ex_p = block_exclusive_scan<unsigned long long>((unsigned long long)L, s_scan, &nlen);
+    const unsigned long long ex_s =
+        block_exclusive_scan<unsigned long long>((unsigned long long)__popc(occ), s_scan, &nocc);
+    const unsigned long long ex_p = block_exclusive_scan<unsigned long long>(lmine, s_scan, &nlen);
     if (threadIdx.x == 0) {
       s_base[0] = nocc ? atomicAdd(&counters[0], nocc) : 0ull;
       s_base[1] = nlen ? atomicAdd(&counters[1], nlen) : 0ull;
     }
     __syncthreads();
-    if (occ) {
-      const unsigned long long sidx = s_base[0] + ex_s;
+    unsigned long long sidx = s_base[0] + ex_s, region = s_base[1] + ex_p;
+#pragma unroll
+    for (int j = 0; j < kAssignItems; ++j) {
+      if (!((occ >> j) & 1u)) continue;
+      const int64_t h = h0 + j * kBlock + threadIdx.x;
       dense[h] = (int32_t)sidx;
       if (rep)
         slot_rep[sidx] = rep[h];
       else
-        slot_key[sidx] = key;
-      slot_region[sidx] = (int64_t)(s_base[1] + ex_p);
+        slot_key[sidx] = keys[h];
+      slot_region[sidx] = (int64_t)region;
+      ++sidx;
+      region += (unsigned long long)L[j];
     }
     __syncthreads();  // s_base is rewritten by the next step
   }
 }
 
-// One block per group: order-preserving compaction of the candidates of the
-// representative row's pivot list that pass the vertex validator of position
-// a, the pivot-arc predicate and every other condition between a and the
-// positions in rmask (rmask == 0: the pivot position alone).  The list is taken kExpandTile entries at a time
-// (4 consecutive ones per thread); every checked list is cut once per piece
-// to the piece's id range, staged in LDS when short enough and searched
-// there, else searched in the cut range.
+// Pieces per group: the group's raw list length (the representative row's
+// pivot list, or the list named by a table-0 key) split into runs of plen
+// entries, into len[s] with per-block sums in bsum (same tiling as
+// k_row_pivot), ready for launch_scan_lengths.
+__global__ __launch_bounds__(kBlock) void k_filter_pieces(DevGraph g,
+                                                          const int32_t* __restrict__ rows,
+                                                          int32_t d,
+                                                          const int2* __restrict__ piv,
+                                                          int32_t nslots,
+                                                          const unsigned long long* __restrict__ slot_key,
+                                                          const int32_t* __restrict__ slot_rep,
+                                                          int32_t plen, int64_t* __restrict__ len,
+                                                          int64_t* __restrict__ bsum) {
+  __shared__ int64_t s_scan[kWaves + 1];
+  int64_t sum = 0;
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    const int64_t s = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+    if (s < nslots) {
+      int32_t v, code;
+      if (slot_rep) {
+        const int64_t i = slot_rep[s];
+        code = piv[i].x;
+        v = rows[i * d + (code >> 2)];
+      } else {
+        const unsigned long long key = slot_key[s];
+        v = (int32_t)(key & 0xffffffffull);
+        code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+      }
+      const int64_t L = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
+      const int64_t n = (L + plen - 1) / plen;
+      len[s] = n;
+      sum += n;
+    }
+  }
+  const int64_t tot = block_sum<int64_t>(sum, s_scan);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// One block per piece of a group (pbase: the exclusive prefix sums of the
+// pieces per group, pbase[nslots] their total; blocks at or past the total
+// exit): order-preserving compaction of the candidates of the piece's part of
+// the representative row's pivot list that pass the vertex validator of
+// position a, the pivot-arc predicate and every other condition between a and
+// the positions in rmask (rmask == 0: the pivot position alone).  A piece is
+// taken kExpandTile entries at a time (4 consecutive ones per thread); every
+// checked list is cut once per tile to the tile's id range, staged in LDS
+// when short enough and searched there, else searched in the cut range.  A
+// one-piece group writes its list to pool + slot_region[s] and its length to
+// fcount[s]; a piece of a longer group writes to tmp at the piece's own
+// offset in the group's region, for k_filter_merge.  Every piece leaves its
+// count in pcnt; pslot[blk] names the block's group (k_filter_map).
 __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
                                                          const uint32_t* __restrict__ abits,
                                                          int32_t a, const int32_t* __restrict__ rows,
                                                          const int2* __restrict__ piv,
-                                                         uint32_t rmask,
+                                                         uint32_t rmask, int32_t nslots,
+                                                         const int64_t* __restrict__ pbase,
+                                                         int32_t plen,
                                                          const unsigned long long* __restrict__ slot_key,
                                                          const int32_t* __restrict__ slot_rep,
                                                          const int64_t* __restrict__ slot_region,
                                                          int32_t* __restrict__ pool,
-                                                         int32_t* __restrict__ fcount) {
+                                                         int32_t* __restrict__ fcount,
+                                                         int32_t* __restrict__ tmp,
+                                                         int32_t* __restrict__ pcnt,
+                                                         const int32_t* __restrict__ pslot) {
   __shared__ int32_t s_scan[kWaves + 1];
   __shared__ int32_t s_f[kMaxK];
   __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
   __shared__ int32_t s_pool[kTilePool];
   __shared__ int32_t s_n;
+  const int64_t blk = blockIdx.x;
+  const int64_t total = pbase[nslots];
+  const int32_t s = pslot[blk];  // read beside the total; used only below it
+  if (blk >= total) return;
+  const int64_t p0 = pbase[s];
+  const int64_t npieces = pbase[s + 1] - p0;
+  const int64_t piece = blk - p0;
   const int32_t d = a;
   int32_t code, pv_v = 0;
   int64_t i = 0;
   if (rmask) {
-    i = slot_rep[blockIdx.x];
+    i = slot_rep[s];
     code = piv[i].x;
   } else {
-    const unsigned long long key = slot_key[blockIdx.x];
+    const unsigned long long key = slot_key[s];
     pv_v = (int32_t)(key & 0xffffffffull);
     code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
   }
@@ -1451,10 +1522,12 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
   __syncthreads();
   const int32_t ncons = s_n;
   const int32_t v = rmask ? s_f[b] : pv_v;
-  const int32_t lo = out_dir ? g.out_off[v] : g.in_off[v];
-  const int32_t hi = out_dir ? g.out_off[v + 1] : g.in_off[v + 1];
+  const int32_t v0 = out_dir ? g.out_off[v] : g.in_off[v];
+  const int32_t v1 = out_dir ? g.out_off[v + 1] : g.in_off[v + 1];
+  const int32_t lo = (int32_t)(v0 + piece * plen);
+  const int32_t hi = (int64_t)v1 - lo > plen ? lo + plen : v1;
   const int32_t* lst = out_dir ? g.out_nbrs : g.in_nbrs;
-  int32_t* dst = pool + slot_region[blockIdx.x];
+  int32_t* dst = npieces == 1 ? pool + slot_region[s] : tmp + slot_region[s] + piece * plen;
   int32_t run = 0;
   for (int32_t base = lo; base < hi; base += kExpandTile) {
     const int32_t end = base + kExpandTile < hi ? base + kExpandTile : hi;
@@ -1548,9 +1621,86 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
     for (int it = 0; it < kExpandItems; ++it)
       if ((keep >> it) & 1u) dst[o++] = c[it];
     run += tot;
-    __syncthreads();  // s_wlo / s_pool are rewritten by the next piece
+    __syncthreads();  // s_wlo / s_pool are rewritten by the next tile
   }
-  if (threadIdx.x == 0) fcount[blockIdx.x] = run;
+  if (threadIdx.x == 0) {
+    if (npieces == 1) fcount[s] = run;
+    pcnt[blk] = run;
+  }
+}
+
+// pslot[pbase[s] .. pbase[s + 1]) = s for every group s.
+__global__ __launch_bounds__(kBlock) void k_filter_map(int32_t nslots,
+                                                       const int64_t* __restrict__ pbase,
+                                                       int32_t* __restrict__ pslot) {
+  for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < nslots;
+       s += (int64_t)gridDim.x * kBlock)
+    for (int64_t j = pbase[s]; j < pbase[s + 1]; ++j) pslot[j] = (int32_t)s;
+}
+
+// Pieces of groups with two or more: each block takes kMergePieces pieces;
+// a thread per piece finds where its survivors go in the group's region (behind
+// those of the pieces before it; the last piece writes the group's length to
+// fcount), then the whole block moves all those survivors from tmp to pool.
+__global__ __launch_bounds__(kBlock) void k_filter_merge(int32_t nslots,
+                                                         const int64_t* __restrict__ pbase,
+                                                         const int64_t* __restrict__ slot_region,
+                                                         const int32_t* __restrict__ tmp,
+                                                         const int32_t* __restrict__ pcnt,
+                                                         const int32_t* __restrict__ pslot,
+                                                         int32_t plen, int32_t* __restrict__ pool,
+                                                         int32_t* __restrict__ fcount) {
+  __shared__ int32_t s_scan[kWaves + 1];
+  __shared__ int32_t s_off[kMergePieces];
+  __shared__ int64_t s_src[kMergePieces], s_dst[kMergePieces];
+  const int64_t total = pbase[nslots];
+  const int64_t blk = (int64_t)blockIdx.x * kMergePieces + threadIdx.x;
+  int32_t n = 0;
+  int64_t src = 0, dst = 0;
+  if (threadIdx.x < kMergePieces && blk < total) {
+    const int32_t s = pslot[blk];
+    const int64_t p0 = pbase[s], np = pbase[s + 1] - p0;
+    if (np > 1) {
+      const int64_t piece = blk - p0;
+      int64_t pre = 0;
+      for (int64_t q = p0; q < blk; ++q) pre += pcnt[q];
+      n = pcnt[blk];
+      src = slot_region[s] + piece * plen;
+      dst = slot_region[s] + pre;
+      if (piece == np - 1) fcount[s] = (int32_t)(pre + n);
+    }
+  }
+  int32_t tot;
+  const int32_t ex = block_exclusive_scan<int32_t>(n, s_scan, &tot);
+  if (threadIdx.x < kMergePieces) {
+    s_off[threadIdx.x] = ex;
+    s_src[threadIdx.x] = src;
+    s_dst[threadIdx.x] = dst;
+  }
+  __syncthreads();
+  // entry of element e: the last piece whose offset is <= e (empty pieces
+  // share the offset of the next non-empty one and come before it)
+  for (int32_t e0 = threadIdx.x; e0 < tot; e0 += 4 * kBlock) {
+    int32_t val[4];
+    int64_t to[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t e = e0 + u * kBlock;
+      if (e < tot) {
+        int32_t l = 0, h = kMergePieces;
+        while (h - l > 1) {
+          const int32_t mid = (l + h) >> 1;
+          if (s_off[mid] <= e) l = mid; else h = mid;
+        }
+        const int32_t k = e - s_off[l];
+        val[u] = tmp[s_src[l] + k];
+        to[u] = s_dst[l] + k;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * kBlock < tot) pool[to[u]] = val[u];
+  }
 }
 
 // Redirect long rows to their filtered list: new lengths go to len[0..r) and
@@ -1842,20 +1992,45 @@ hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  k_filter_assign<<<grid_for(H, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+  k_filter_assign<<<grid_for(H, kAssignTile, kMaxGridSimple), kBlock, 0, stream>>>(
       g, rows, d, piv, keys, H, rmask ? rep : nullptr, dense, slot_key, slot_rep, slot_region,
       counters);
   return hipGetLastError();
 }
 
+hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t d,
+                                const int2* piv, int32_t nslots,
+                                const unsigned long long* slot_key, const int32_t* slot_rep,
+                                int32_t plen, int64_t* pbase, int64_t* bsum, int32_t* pslot,
+                                hipStream_t stream) {
+  if (nslots <= 0) return hipSuccess;
+  const int nb = (int)(((int64_t)nslots + kPivotTile - 1) / kPivotTile);
+  k_filter_pieces<<<nb, kBlock, 0, stream>>>(g, rows, d, piv, nslots, slot_key, slot_rep, plen,
+                                             pbase, bsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan_lengths(pbase, nslots, bsum, stream);
+  if (e != hipSuccess) return e;
+  k_filter_map<<<grid_for(nslots, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(nslots, pbase,
+                                                                              pslot);
+  return hipGetLastError();
+}
+
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                                int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
-                               int32_t nslots, const unsigned long long* slot_key,
-                               const int32_t* slot_rep, const int64_t* slot_region,
-                               int32_t* pool, int32_t* fcount, hipStream_t stream) {
-  if (nslots <= 0) return hipSuccess;
-  k_filter_lists<<<nslots, kBlock, 0, stream>>>(g, plan, abits, a, rows, piv, rmask, slot_key,
-                                                slot_rep, slot_region, pool, fcount);
+                               int32_t nslots, const int64_t* pbase, int32_t plen, int32_t grid,
+                               const unsigned long long* slot_key, const int32_t* slot_rep,
+                               const int64_t* slot_region, int32_t* pool, int32_t* fcount,
+                               int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
+                               hipStream_t stream) {
+  if (nslots <= 0 || grid <= 0) return hipSuccess;
+  k_filter_lists<<<grid, kBlock, 0, stream>>>(g, plan, abits, a, rows, piv, rmask, nslots, pbase,
+                                              plen, slot_key, slot_rep, slot_region, pool, fcount,
+                                              tmp, pcnt, pslot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || tmp == nullptr) return e;
+  k_filter_merge<<<(grid + kMergePieces - 1) / kMergePieces, kBlock, 0, stream>>>(
+      nslots, pbase, slot_region, tmp, pcnt, pslot, plen, pool, fcount);
   return hipGetLastError();
 }
 

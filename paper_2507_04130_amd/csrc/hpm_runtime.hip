@@ -107,6 +107,9 @@ struct Workspace {
   // sums; shared by all depths the hash table and slot descriptors
   DevBuf fpool[kMaxK], off2[kMaxK];
   DevBuf fkeys, frep, fdense, fslot_key, fslot_rep, fslot_region, fcount;
+  // the filter's pieces: per-group prefix sums, per-piece counts and groups,
+  // and the staging area of groups split over several blocks
+  DevBuf fpbase, fpbsum, fpcnt, fpslot, ftmp;
   // per depth: prefix sums of short-row lengths and of long-row tile counts
   DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
   unsigned long long* host = nullptr;  // pinned readback slots
@@ -121,7 +124,8 @@ struct Workspace {
     size_t s = plan.bytes + vbits.bytes + counters.bytes + partials.bytes +
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
-               fslot_region.bytes + fcount.bytes;
+               fslot_region.bytes + fcount.bytes + fpbase.bytes + fpbsum.bytes + fpcnt.bytes +
+               fpslot.bytes + ftmp.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
            off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
@@ -133,6 +137,7 @@ struct Workspace {
     fkeys.release(); frep.release(); fdense.release(); fslot_key.release(); fslot_rep.release();
     fslot_region.release();
     fcount.release();
+    fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); ftmp.release();
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
       fpool[d].release(); off2[d].release();
@@ -425,6 +430,7 @@ enum : int {
   kCntTotal = 0, kCntOverflow = 1, kCntEmit = 2, kCntCursor = 3,
   kCntSlots = 4,        // host slot of read_i64
   kCntFilterSlots = 8,  // 8, 9: groups and pool entries; 10..12: keys of the filter tables
+  kHostPieces = 13,     // host slot 13: blocks of the filter's list pass
   kHostSplit = 14,      // host slots 14, 15: short work and long tiles of a split
   kCntNum = 16          // counter slots on the device and in pinned host memory
 };
@@ -661,20 +667,45 @@ struct Matcher {
     if (t_use < 0 && groups(0)) t_use = 0;
     const uint32_t use_mask = t_use > 0 ? masks[t_use] : 0u;
     if (nslots == 0) return;
-    const uint64_t more = extra(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4) +
-                          extra(W->fcount, (size_t)nslots * 4) +
-                          extra(W->off2[d], (size_t)(r + 1) * 8);
+    // Long lists are split over several blocks (pieces of kFilterPiece
+    // entries) when the staging area fits the budget, else one block per group.
+    const int64_t nbs = (nslots + hpm::kPivotTile - 1) / hpm::kPivotTile + 1;
+    const int64_t grid_split = nslots + pool / hpm::kFilterPiece;
+    uint64_t more = extra(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4) +
+                    extra(W->fcount, (size_t)nslots * 4) +
+                    extra(W->off2[d], (size_t)(r + 1) * 8) +
+                    extra(W->fpbase, (size_t)(nslots + 1) * 8) + extra(W->fpbsum, (size_t)nbs * 8);
     if (planned + more > budget) return;
+    const uint64_t split_more = extra(W->ftmp, (size_t)std::max<int64_t>(pool, 1) * 4) +
+                                extra(W->fpcnt, (size_t)grid_split * 4) +
+                                extra(W->fpslot, (size_t)grid_split * 4);
+    const bool split = grid_split > nslots && grid_split < INT32_MAX &&
+                       planned + more + split_more <= budget;
+    const int32_t plen = split ? hpm::kFilterPiece : INT32_MAX;
+    const int64_t grid = split ? grid_split : nslots;
     need(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4);
     need(W->fcount, (size_t)nslots * 4);
     need(W->off2[d], (size_t)(r + 1) * 8);
+    need(W->fpbase, (size_t)(nslots + 1) * 8);
+    need(W->fpbsum, (size_t)nbs * 8);
+    need(W->fpcnt, (size_t)grid * 4);
+    need(W->fpslot, (size_t)grid * 4);
+    if (split) need(W->ftmp, (size_t)std::max<int64_t>(pool, 1) * 4);
     int64_t* off2 = W->off2[d].as<int64_t>();
+    const unsigned long long* skey = W->fslot_key.as<unsigned long long>();
+    const int32_t* srep = use_mask ? W->fslot_rep.as<int32_t>() : nullptr;
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_filter_pieces(g, rows, d, piv, (int32_t)nslots, skey, srep, plen,
+                                       W->fpbase.as<int64_t>(), W->fpbsum.as<int64_t>(),
+                                       W->fpslot.as<int32_t>(), stream);
+    });
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_lists(g, dplan(), bits(d), d, rows, piv, use_mask,
-                                      (int32_t)nslots, W->fslot_key.as<unsigned long long>(),
-                                      use_mask ? W->fslot_rep.as<int32_t>() : nullptr,
-                                      W->fslot_region.as<int64_t>(), W->fpool[d].as<int32_t>(),
-                                      W->fcount.as<int32_t>(), stream);
+                                      (int32_t)nslots, W->fpbase.as<int64_t>(), plen,
+                                      (int32_t)grid, skey, srep, W->fslot_region.as<int64_t>(),
+                                      W->fpool[d].as<int32_t>(), W->fcount.as<int32_t>(),
+                                      split ? W->ftmp.as<int32_t>() : nullptr,
+                                      W->fpcnt.as<int32_t>(), W->fpslot.as<int32_t>(), stream);
     });
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_apply(rows, (int32_t)r, d, piv, off, off2, hpm::kFilterMinLen,
@@ -686,7 +717,11 @@ struct Matcher {
     });
     launch(HPM_K_PREFIX_SUM,
            [&] { return hpm::launch_scan_lengths(off2, (int32_t)r, W->bsum[d].as<int64_t>(), stream); });
-    *work = read_i64(off2 + r);
+    hip_check(hipMemcpyAsync(W->host + kHostPieces, W->fpbase.as<int64_t>() + nslots,
+                             sizeof(int64_t), hipMemcpyDeviceToHost, stream),
+              "readback");
+    *work = read_i64(off2 + r);  // synchronises: the piece total has landed too
+    st.filter_pieces += W->host[kHostPieces];
     *offp = off2;
     *fpool = W->fpool[d].as<int32_t>();
     done[d] = use_mask ? use_mask : hpm::kDonePivot;

@@ -63,7 +63,7 @@ class _Stats(ctypes.Structure):
                 ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1)),
                 ("overlap_removed", ctypes.c_uint64), ("counted_rows", ctypes.c_uint64),
                 ("counted_work", ctypes.c_uint64), ("filter_rows", ctypes.c_uint64),
-                ("filter_entries", ctypes.c_uint64)]
+                ("filter_entries", ctypes.c_uint64), ("filter_pieces", ctypes.c_uint64)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -395,6 +395,7 @@ def last_stats() -> dict:
         "overlap_removed": s.overlap_removed,
         "counted_rows": s.counted_rows, "counted_work": s.counted_work,
         "filter_rows": s.filter_rows, "filter_entries": s.filter_entries,
+        "filter_pieces": s.filter_pieces,
     }
 
 

@@ -15,7 +15,7 @@ import oracle
 import paper_2507_04130_amd as hpm
 from paper_2507_04130_amd import hpm as hb
 from synth import configs
-from synth.graphs import erdos_renyi, from_dense, permute_vertices, rmat
+from synth.graphs import erdos_renyi, from_dense, graph_from_arcs, permute_vertices, rmat
 from synth.patterns import EQ, GE, ISO, MONO, MOTIFS, make_pattern, motif, random_pattern
 from tests import pins
 from tests.cases import (load_hand_example, random_small_graph, random_small_pattern)
@@ -318,6 +318,47 @@ def test_prefiltered_lists_change_nothing():
         assert oracle.fingerprint(r1) == want.fingerprint
         say(f"filter {name}/{mode}: count={c1} lists={hpm.last_stats()['filtered_lists']}")
     assert used > 0
+
+
+def hub_graph(seed=41, n=6000, m=24000, hubs=2, deg=2500):
+    """Sparse uniform arcs plus `hubs` vertices with `deg` out-neighbours and
+    `deg` other in-neighbours each: candidate lists longer than one filter
+    piece that many partial mappings share."""
+    rng = np.random.default_rng(seed)
+    src, dst = [rng.integers(0, n, m)], [rng.integers(0, n, m)]
+    for h in range(hubs):
+        t = rng.choice(np.arange(hubs, n), 2 * deg, replace=False)
+        src += [np.full(deg, h), t[deg:]]
+        dst += [t[:deg], np.full(deg, h)]
+    src, dst = np.concatenate(src), np.concatenate(dst)
+    keep = src != dst
+    keys = np.unique(src[keep] * n + dst[keep])
+    return graph_from_arcs(n, keys // n, keys % n, [rng.integers(0, 4, n)],
+                           lambda mm: [rng.integers(0, 2, mm)])
+
+
+def test_prefilter_split_over_pieces_changes_nothing():
+    # Hub lists of 2500 entries are filtered by several blocks each (pieces of
+    # 1024 entries, then merged in order); rows must equal the unfiltered path
+    # and the oracle's count and fingerprint.
+    g = hub_graph()
+    dg = hpm.Graph.from_host(g)
+    lists = pieces = 0
+    for name, mode in (("ffl_tail", MONO), ("ffl_tail", ISO), ("cycle4", ISO)):
+        p = motif(name)
+        c0, r0 = gpu_rows(dg, p, mode, flags=hpm.F_NO_FILTER)
+        c1, r1 = gpu_rows(dg, p, mode)
+        st = hpm.last_stats()
+        lists += st["filtered_lists"]
+        pieces += st["filter_pieces"]
+        assert c0 == c1
+        np.testing.assert_array_equal(r0, r1)
+        want = oracle.match(g, p, mode, threads=8, rows=False)
+        assert c1 == want.count
+        assert oracle.fingerprint(r1) == want.fingerprint
+        say(f"hub filter {name}/{mode}: count={c1} lists={st['filtered_lists']} "
+            f"pieces={st['filter_pieces']}")
+    assert pieces > lists > 0
 
 
 def test_batch_equals_single_and_oracle():
