@@ -27,6 +27,8 @@ constexpr int kFilterPiece = kExpandTile;  // list entries per block of the filt
 constexpr int kAssignItems = 16;     // hash slots per thread and step when numbering groups
 constexpr int kAssignTile = kBlock * kAssignItems;
 constexpr int kMergePieces = 64;     // filter pieces per block when closing the gaps
+constexpr int kCountStage = 2048;    // filtered-list entries a wavefront stages in the count pass
+constexpr int kCountNbrMax = 2048;   // neighbours a wavefront walks for one row in the count pass
 constexpr int kTailWords = 1024;      // tail-flag bitmap words a scan tile stages in LDS
 constexpr int kValidatorSpan = 256;   // consecutive vertices a wavefront validates per step
 constexpr int kAlignMin = 512;        // rows with this many candidates get tiles of their own
@@ -151,13 +153,17 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
                          const int64_t* toff, uint32_t done, int out_mode, int32_t* out,
                          unsigned long long* cursor, unsigned long long out_cap,
                          unsigned long long* partials, int grid, hipStream_t stream);
-// Last-level count of r rows whose filtered lists leave only injectivity to
-// check (filtered rows: list length minus the row's images found in the list;
-// other rows: every candidate checked); per-block sums into partials[grid].
+// Last-level count of r rows whose filtered lists enforce every arc-related
+// position: filtered rows are counted as list length minus the list members
+// that are the row's own images or (umask != 0, induced isomorphism)
+// neighbours of its images at the positions in umask; other rows check every
+// candidate; per-block sums into partials[grid].  With umask != 0, rest[0..r)
+// receives the list length of each filtered row left to the tiled extension
+// (its images in umask have more than kCountNbrMax neighbours), else 0.
 hipError_t launch_count_rows(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                              int32_t d, const int32_t* rows, const int64_t* off, const int2* piv,
-                             const int32_t* fpool, int32_t r, unsigned long long* partials,
-                             int grid, hipStream_t stream);
+                             const int32_t* fpool, int32_t r, uint32_t umask, int64_t* rest,
+                             unsigned long long* partials, int grid, hipStream_t stream);
 // Split rows by list length (prefix sums off[0..r]): soff[0..r] = prefix sums
 // of the lengths of rows shorter than kAlignMin (long rows count 0), toff[0..r]
 // = prefix sums of the tile counts of long rows; sbsum/tbsum as for

@@ -1111,79 +1111,168 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   }
 }
 
-// Last level, count only, after a filter that left no relation to check on
-// filtered rows (monomorphism, every arc-related position enforced): such a
-// row's embeddings are its filtered list minus the row's own images found in
-// it (injectivity), so it costs d binary searches instead of one item per
-// candidate.  Rows left unfiltered (short lists, or a group-key collision)
-// check their candidates one by one.  One lane per row; per-block sums go to
+// Last level, count only, after a filter that enforced every condition
+// between the new position and the mapped positions it is tied to by a
+// pattern arc.  What a filtered row still has to check is injectivity and,
+// for induced isomorphism, the absence of arcs (either direction) between
+// the new vertex and the images of the positions in umask.  Its count is
+// therefore its filtered list's length minus the list members that are the
+// row's own images or neighbours of an image in umask:
+//  * umask == 0 (SUB false): d binary searches in the list, one lane per row;
+//  * else (SUB true), when those images have at most kCountNbrMax neighbours in all,
+//    the block queues the row and a wavefront walks the neighbours, looking
+//    each up in the list (staged in LDS when it has at most kCountStage
+//    entries; neighbouring rows often share one list, staged once).  A
+//    neighbour is taken off once: not if it is an image, nor if an earlier
+//    list (by position, out before in) holds it too.  Rows with more
+//    neighbours are not counted here: rest[i] = their list length (0 for
+//    every other row) for the tiled extension.
+// Rows left unfiltered (short lists, or a group-key collision) check their
+// candidates one by one in their lane.  Per-block sums go to
 // partials[blockIdx].
+template <bool SUB>
 __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan* __restrict__ P,
                                                        const uint32_t* __restrict__ abits,
                                                        int32_t d, const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ off,
                                                        const int2* __restrict__ piv,
                                                        const int32_t* __restrict__ fpool,
-                                                       int32_t r,
+                                                       int32_t r, uint32_t umask,
+                                                       int64_t* __restrict__ rest,
                                                        unsigned long long* __restrict__ partials) {
-  __shared__ unsigned long long s_scan[kWaves + 1];
+  __shared__ long long s_scan[kWaves + 1];
+  __shared__ int32_t s_iscan[kWaves + 1];
+  __shared__ int32_t s_q[kBlock];
+  __shared__ int32_t s_list[kWaves * kCountStage];
   const int32_t a = d;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
   const bool iso = P->mode == 0;
-  unsigned long long my_count = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
-       i += (int64_t)gridDim.x * kBlock) {
-    const int64_t o = off[i];
-    const int32_t len = (int32_t)(off[i + 1] - o);
-    if (len == 0) continue;
-    const int2 pv = piv[i];
-    const int32_t b = pv.x >> 2;
-    const bool via_out = (pv.x & 1) != 0;
-    const int32_t* row = rows + i * d;
-    if (pv.x & 2) {
-      int32_t cnt = len;
-      for (int q = 0; q < d; ++q)
-        if (find_in(fpool, pv.y, pv.y + len, row[q]) >= 0) --cnt;
-      my_count += (unsigned long long)cnt;
-      continue;
-    }
-    for (int32_t j = 0; j < len; ++j) {
-      const int32_t pos = pv.y + j;
-      const int32_t c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
-      bool ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
-      if (ok) {
-        if (via_out) {
-          if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
-        } else if (P->amask[a][b]) {
-          ok = arc_ok_in(g, P, a, b, pos);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int32_t* wl = s_list + wave * kCountStage;
+  long long acc = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < r; i0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    bool queue = false;
+    if (i < r) {
+      int64_t left = 0;
+      const int64_t o = off[i];
+      const int32_t len = (int32_t)(off[i + 1] - o);
+      const int2 pv = len > 0 ? piv[i] : make_int2(0, 0);
+      const int32_t* row = rows + i * d;
+      if (len > 0 && (pv.x & 2)) {
+        if (!SUB) {
+          int32_t cnt = len;
+          for (int q = 0; q < d; ++q)
+            if (find_in(fpool, pv.y, pv.y + len, row[q]) >= 0) --cnt;
+          acc += cnt;
+        } else {
+          int64_t nbrs = 0;
+          for (int q = 0; q < d; ++q)
+            if ((umask >> q) & 1u) {
+              const int32_t f = row[q];
+              nbrs += (int64_t)(g.out_off[f + 1] - g.out_off[f]) + (g.in_off[f + 1] - g.in_off[f]);
+            }
+          if (nbrs <= kCountNbrMax)
+            queue = true;
+          else
+            left = len;
+        }
+      } else if (len > 0) {
+        const int32_t b = pv.x >> 2;
+        const bool via_out = (pv.x & 1) != 0;
+        for (int32_t j = 0; j < len; ++j) {
+          const int32_t pos = pv.y + j;
+          const int32_t c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
+          bool ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
+          if (ok) {
+            if (via_out) {
+              if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
+            } else if (P->amask[a][b]) {
+              ok = arc_ok_in(g, P, a, b, pos);
+            }
+          }
+          for (int q = 0; q < d && ok; ++q) ok = row[q] != c;
+          for (int q = 0; q < d && ok; ++q) {
+            const int32_t fq = row[q];
+            if ((fw >> q) & 1u) {
+              if (!(q == b && via_out)) {
+                const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
+                ok = e >= 0 && arc_ok(g, P, q, a, e);
+              }
+            } else if (iso) {
+              ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
+            }
+            if (!ok) break;
+            if ((bw >> q) & 1u) {
+              if (!(q == b && !via_out)) {
+                const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
+                ok = e >= 0 && arc_ok_in(g, P, a, q, e);
+              }
+            } else if (iso) {
+              ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
+            }
+          }
+          acc += ok ? 1 : 0;
         }
       }
-      for (int q = 0; q < d && ok; ++q) ok = row[q] != c;
-      for (int q = 0; q < d && ok; ++q) {
+      if (rest) rest[i] = left;
+    }
+    if (!SUB) continue;  // no queue
+    int32_t nq;
+    const int32_t qpos = block_exclusive_scan<int32_t>(queue ? 1 : 0, s_iscan, &nq);
+    if (queue) s_q[qpos] = threadIdx.x;
+    __syncthreads();
+    // each wavefront takes a contiguous share of the queue, in row order
+    const int32_t qb = wave * nq / kWaves, qe = (wave + 1) * nq / kWaves;
+    int32_t st_at = -1, st_len = -1;
+    for (int32_t qi = qb; qi < qe; ++qi) {
+      const int64_t ri = i0 + s_q[qi];
+      const int32_t len = (int32_t)(off[ri + 1] - off[ri]);
+      const int32_t lst = piv[ri].y;
+      const int32_t* row = rows + ri * d;
+      const bool staged = len <= kCountStage;
+      if (staged && (lst != st_at || len != st_len)) {
+        wave_sync();  // earlier readers of wl are done
+        for (int32_t x = lane; x < len; x += 64) wl[x] = fpool[lst + x];
+        wave_sync();
+        st_at = lst;
+        st_len = len;
+      }
+      int32_t hits = 0;
+      if (lane < d) {
+        const int32_t y = row[lane];
+        if (staged ? lds_find(wl, len, y) >= 0 : find_in(fpool, lst, lst + len, y) >= 0) ++hits;
+      }
+      for (int q = 0; q < d; ++q) {
+        if (!((umask >> q) & 1u)) continue;
         const int32_t fq = row[q];
-        if ((fw >> q) & 1u) {
-          if (!(q == b && via_out)) {
-            const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
-            ok = e >= 0 && arc_ok(g, P, q, a, e);
+        for (int dir = 0; dir < 2; ++dir) {
+          const int32_t* nb = dir ? g.in_nbrs : g.out_nbrs;
+          const int32_t lo = dir ? g.in_off[fq] : g.out_off[fq];
+          const int32_t hi = dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+          for (int32_t x = lo + lane; x < hi; x += 64) {
+            const int32_t y = nb[x];
+            bool hit = staged ? lds_find(wl, len, y) >= 0 : find_in(fpool, lst, lst + len, y) >= 0;
+            for (int p = 0; p < d && hit; ++p) hit = row[p] != y;
+            if (hit && dir) hit = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], y) < 0;
+            for (int q2 = 0; q2 < q && hit; ++q2) {
+              if (!((umask >> q2) & 1u)) continue;
+              const int32_t f2 = row[q2];
+              hit = find_in(g.out_nbrs, g.out_off[f2], g.out_off[f2 + 1], y) < 0 &&
+                    find_in(g.in_nbrs, g.in_off[f2], g.in_off[f2 + 1], y) < 0;
+            }
+            hits += hit ? 1 : 0;
           }
-        } else if (iso) {
-          ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
-        }
-        if (!ok) break;
-        if ((bw >> q) & 1u) {
-          if (!(q == b && !via_out)) {
-            const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
-            ok = e >= 0 && arc_ok_in(g, P, a, q, e);
-          }
-        } else if (iso) {
-          ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
         }
       }
-      my_count += ok ? 1ull : 0ull;
+      acc -= hits;
+      if (lane == 0) acc += len;
     }
+    __syncthreads();  // s_q is rewritten by the next step
   }
-  const unsigned long long tot = block_sum<unsigned long long>(my_count, s_scan);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  const long long tot = block_sum<long long>(acc, s_scan);
+  if (threadIdx.x == 0) partials[blockIdx.x] = (unsigned long long)tot;
 }
 
 // Rows with at least kAlignMin candidates get tiles of their own: soff[i] is
@@ -1262,6 +1351,13 @@ __device__ __forceinline__ uint32_t key_hash(uint64_t x) {
 
 constexpr unsigned long long kEmptyKey = ~0ull;
 
+// The value of lane - 1 (lane 0 gets its own).
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long x) {
+  const int lo = __shfl_up((int)(uint32_t)x, 1, 64);
+  const int hi = __shfl_up((int)(uint32_t)(x >> 32), 1, 64);
+  return (unsigned long long)(uint32_t)lo | ((unsigned long long)(uint32_t)hi << 32);
+}
+
 // Group key of row i (see above).
 __device__ __forceinline__ unsigned long long row_key(const int32_t* __restrict__ rows, int64_t i,
                                                       int32_t d, int32_t code, uint32_t rmask) {
@@ -1301,13 +1397,20 @@ __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restr
       const uint32_t m = t == 0 ? 0u : (t == 1 ? mask1 : mask2);
       if (t > 0 && m == 0) continue;  // uniform
       bool fresh = false;
-      if (ins) {
+      const unsigned long long key = ins ? row_key(rows, i, d, piv[i].x, m) : kEmptyKey;
+      // neighbouring rows often share a key: the lane before inserts it
+      const unsigned long long before = shfl_up_u64(key);
+      if (ins && !(lane > 0 && before == key)) {
         unsigned long long* tab = keys + (size_t)t * H;
-        const unsigned long long key = row_key(rows, i, d, piv[i].x, m);
         uint32_t h = key_hash(key) & (H - 1);
         while (true) {  // H exceeds the number of rows, so a free slot exists
-          const unsigned long long prev = atomicCAS(&tab[h], kEmptyKey, key);
-          if (prev == kEmptyKey) fresh = true;
+          // a slot only ever goes from empty to a key, so a plain read that
+          // shows a key is final; an empty one is settled by the CAS
+          unsigned long long prev = tab[h];
+          if (prev == kEmptyKey) {
+            prev = atomicCAS(&tab[h], kEmptyKey, key);
+            if (prev == kEmptyKey) fresh = true;
+          }
           if (prev == kEmptyKey || prev == key) break;
           h = (h + 1) & (H - 1);
         }
@@ -1332,7 +1435,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_rep(const int32_t* __restrict
        i += (int64_t)gridDim.x * kBlock) {
     if (off[i + 1] - off[i] < min_len) continue;
     const unsigned long long key = row_key(rows, i, d, piv[i].x, rmask);
-    atomicMin(&rep[table_find(keys, H, key)], (int32_t)i);
+    int32_t* slot = &rep[table_find(keys, H, key)];
+    if (*slot > (int32_t)i) atomicMin(slot, (int32_t)i);  // rep only decreases
   }
 }
 
@@ -1950,10 +2054,15 @@ hipError_t launch_expand(const DevGraph& g, const DevPlan* plan, const uint32_t*
 
 hipError_t launch_count_rows(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                              int32_t d, const int32_t* rows, const int64_t* off, const int2* piv,
-                             const int32_t* fpool, int32_t r, unsigned long long* partials,
-                             int grid, hipStream_t stream) {
+                             const int32_t* fpool, int32_t r, uint32_t umask, int64_t* rest,
+                             unsigned long long* partials, int grid, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
-  k_count_rows<<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r, partials);
+  if (umask)
+    k_count_rows<true><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
+                                                    umask, rest, partials);
+  else
+    k_count_rows<false><<<grid, kBlock, 0, stream>>>(g, plan, abits, d, rows, off, piv, fpool, r,
+                                                     umask, rest, partials);
   return hipGetLastError();
 }
 

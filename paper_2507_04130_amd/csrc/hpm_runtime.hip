@@ -110,6 +110,8 @@ struct Workspace {
   // the filter's pieces: per-group prefix sums, per-piece counts and groups,
   // and the staging area of groups split over several blocks
   DevBuf fpbase, fpbsum, fpcnt, fpslot, ftmp;
+  // count pass: list lengths left to the tiled last level, and their block sums
+  DevBuf crest, cbsum;
   // per depth: prefix sums of short-row lengths and of long-row tile counts
   DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
   unsigned long long* host = nullptr;  // pinned readback slots
@@ -125,7 +127,7 @@ struct Workspace {
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
                fslot_region.bytes + fcount.bytes + fpbase.bytes + fpbsum.bytes + fpcnt.bytes +
-               fpslot.bytes + ftmp.bytes;
+               fpslot.bytes + ftmp.bytes + crest.bytes + cbsum.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
            off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
@@ -138,6 +140,7 @@ struct Workspace {
     fslot_region.release();
     fcount.release();
     fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); ftmp.release();
+    crest.release(); cbsum.release();
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
       fpool[d].release(); off2[d].release();
@@ -439,6 +442,11 @@ enum : int {
 // depth has at least this many candidates.
 constexpr int64_t kSplitMinWork = int64_t(1) << 22;
 
+// Induced isomorphism counts filtered rows from their lists (subtracting the
+// neighbours of images they must not touch) only when the rows average at
+// least this many candidates.
+constexpr int64_t kCountMinPerRow = 64;
+
 // Pre-filter pivot lists only when a depth has at least this many candidates.
 constexpr int64_t kFilterMinWork = int64_t(1) << 22;
 
@@ -730,13 +738,23 @@ struct Matcher {
     st.filter_entries += (uint64_t)pool;
   }
 
-  // Monomorphism, filter applied at depth d and every arc-related position
-  // enforced by the filtered lists (so a filtered row only needs injectivity).
-  bool counts_by_rows(int32_t d) const {
-    if (host_plan.mode == HPM_ISO || done[d] == 0) return false;
-    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & ((1u << d) - 1u);
-    if (done[d] == hpm::kDonePivot) return __builtin_popcount(related) == 1;
-    return (related & ~done[d]) == 0;
+  // Filter applied at depth d with every arc-related position enforced by the
+  // filtered lists: a filtered row then only needs injectivity and, for
+  // induced isomorphism, non-arcs to the positions left in *umask.
+  bool counts_by_rows(int32_t d, uint32_t* umask) const {
+    if (done[d] == 0) return false;
+    const uint32_t all = (1u << d) - 1u;
+    const uint32_t related = (host_plan.fwd[d] | host_plan.bwd[d]) & all;
+    uint32_t covered;
+    if (done[d] == hpm::kDonePivot) {
+      if (__builtin_popcount(related) != 1) return false;
+      covered = related;  // the pivot is the one related position
+    } else {
+      if ((related & ~done[d]) != 0) return false;
+      covered = done[d];
+    }
+    *umask = host_plan.mode == HPM_ISO ? (all & ~covered) : 0u;
+    return true;
   }
 
   // Separate rows with at least kAlignMin candidates (row-aligned tiles) from
@@ -790,23 +808,44 @@ struct Matcher {
     if (filter && work >= kFilterMinWork) filter_pivots(d, rows, r, piv, off, &offp, &fpool, &work);
     st.work[d] += (uint64_t)work;
     if (work == 0) return;
-    if (d == k - 1 && !maps && counts_by_rows(d)) {
-      // every condition is in the filtered lists: each row's count follows
-      // from its list length and its own images
+    uint32_t umask = 0;
+    // Walking neighbours pays only against long lists: with few candidates
+    // per row the tiled extension is faster.
+    if (d == k - 1 && !maps && counts_by_rows(d, &umask) &&
+        (umask == 0 || work >= kCountMinPerRow * r)) {
+      // every arc condition is in the filtered lists: each row's count
+      // follows from its list length, its own images and (induced
+      // isomorphism) the neighbours of the images it must not touch
       const int grid = grid_for(r, hpm::kBlock);
       unsigned long long* parts = W->partials.as<unsigned long long>();
-      st.counted_rows += (uint64_t)r;
-      st.counted_work += (uint64_t)work;
+      int64_t* rest = nullptr;
+      if (umask) {
+        need(W->crest, (size_t)(r + 1) * sizeof(int64_t));
+        need(W->cbsum, (size_t)((r + hpm::kPivotTile - 1) / hpm::kPivotTile + 1) * sizeof(int64_t));
+        rest = W->crest.as<int64_t>();
+      }
       launch(HPM_K_LAST_LEVEL, [&] {
         return hpm::launch_count_rows(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r,
-                                      parts, grid, stream);
+                                      umask, rest, parts, grid, stream);
       });
       launch(HPM_K_REDUCE, [&] {
         return hpm::launch_reduce_counts(parts, grid, counters() + kCntTotal,
                                          reinterpret_cast<uint32_t*>(counters() + kCntOverflow),
                                          stream);
       });
-      return;
+      int64_t left = 0;
+      if (umask) {
+        launch(HPM_K_PREFIX_SUM, [&] {
+          return hpm::launch_rows2_compact(rest, (int32_t)r, W->cbsum.as<int64_t>(), stream);
+        });
+        left = read_i64(rest + r);
+      }
+      st.counted_rows += (uint64_t)r;
+      st.counted_work += (uint64_t)(work - left);
+      if (left == 0) return;
+      // rows whose images have many neighbours: the tiled last level below
+      offp = rest;
+      work = left;
     }
     if (d == k - 1) {
       int64_t S = work, T = 0;

@@ -317,6 +317,8 @@ def test_prefiltered_lists_change_nothing():
         assert c1 == want.count
         assert oracle.fingerprint(r1) == want.fingerprint
         say(f"filter {name}/{mode}: count={c1} lists={hpm.last_stats()['filtered_lists']}")
+        # count only: the last level may count filtered rows from their lists
+        assert hpm.match(dg, p, mode)[0] == want.count
     assert used > 0
 
 
@@ -359,6 +361,28 @@ def test_prefilter_split_over_pieces_changes_nothing():
         say(f"hub filter {name}/{mode}: count={c1} lists={st['filtered_lists']} "
             f"pieces={st['filter_pieces']}")
     assert pieces > lists > 0
+
+
+def test_counts_from_filtered_lists_equal_the_oracle():
+    # Count-only last levels whose filtered lists enforce every arc-related
+    # position: monomorphism subtracts the rows' own images, induced
+    # isomorphism also the neighbours of the images it must not touch (a
+    # wavefront per row, or the tiled extension for hub neighbourhoods).
+    g = hub_graph()
+    dg = hpm.Graph.from_host(g)
+    counted = {ISO: 0, MONO: 0}
+    for name, mode in (("star3_back", ISO), ("star3_back", MONO), ("ffl_tail", ISO),
+                       ("cycle4", ISO)):
+        p = motif(name)
+        c1, _ = hpm.match(dg, p, mode)
+        st = hpm.last_stats()
+        counted[mode] += st["counted_rows"]
+        c0, _ = hpm.match(dg, p, mode, flags=hpm.F_NO_FILTER)
+        want = oracle.match(g, p, mode, threads=8, rows=False)
+        say(f"hub count {name}/{mode}: {c1} counted_rows={st['counted_rows']} "
+            f"counted_work={st['counted_work']} work={st['work'][:p.k]}")
+        assert c1 == c0 == want.count
+    assert counted[ISO] > 0 and counted[MONO] > 0
 
 
 def test_batch_equals_single_and_oracle():
