@@ -265,11 +265,10 @@ def main():
 
     extra_flags = hpm.F_OVERLAP if args.overlap else 0
 
-    def step(timing):
+    def step(timing_flags):
         counts, stats = [], []
         for p, mode in runs:
-            c, _ = hpm.match(dg, p, mode, stream=stream,
-                             flags=(hpm.F_TIMING if timing else 0) | extra_flags)
+            c, _ = hpm.match(dg, p, mode, stream=stream, flags=timing_flags | extra_flags)
             counts.append(c)
             stats.append(hpm.last_stats())
         return counts, stats
@@ -380,19 +379,39 @@ def main():
         args.steps, args.warmup = 1, 0     # one trace replay at the highest rate
     else:
         for i in range(args.warmup):
-            counts, _ = step(False)
+            counts, _ = step(0)
             log(f"warmup {i}: counts={counts}")
+        # One step with events around every launch, before the timed region:
+        # per-family times of the whole path, and the family that dominates.
+        # The timed steps then record events only around that family and the
+        # arc scan (two event records per timed launch cost the step time).
+        _, prof_stats = step(hpm.F_TIMING)
+        prof_ms = {}
+        for st in prof_stats:
+            for kname, ms in st["kernel_ms"].items():
+                prof_ms[kname] = prof_ms.get(kname, 0.0) + ms
+        costed_kinds = ("vertex_validator", "edge_scan", "expand", "last_level", "filter")
+        dom_kind = max(costed_kinds, key=lambda k: prof_ms.get(k, 0.0))
+        timed_flags = hpm.F_TIMING | hpm.F_TIMING_KINDS(dom_kind, "edge_scan")
+        log(f"profile step: {({k: round(v, 3) for k, v in prof_ms.items() if v})}; "
+            f"timing {dom_kind} and edge_scan in the timed steps")
+        extra["kernel_ms_per_step_all_families"] = {k: round(v, 4) for k, v in prof_ms.items()}
+        extra["kernel_ms_source"] = ("kernel_ms_per_step_all_families: one step with events "
+                                     "around every launch, before the timed steps; "
+                                     "kernel_ms_per_step and roofline: the timed steps, "
+                                     f"events around {dom_kind} and edge_scan only")
         torch.cuda.synchronize()
         all_stats = []
         t_start = time.perf_counter()
         for i in range(args.steps):
-            counts, stats = step(True)
+            counts, stats = step(timed_flags)
             all_stats.extend(stats)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         log(f"timed {args.steps} steps in {elapsed:.3f}s")
         timed_steps = args.steps
 
+    per_query_stats = prof_stats if (not batch and not serve) else all_stats[-len(runs):]
     matches_per_step = sum(counts)
     ms_per_step = 1000.0 * elapsed / args.steps
     value = matches_per_step * args.steps / elapsed
@@ -444,7 +463,7 @@ def main():
                        "filtered_lists": st["filtered_lists"],
                        "overlap_removed": st["overlap_removed"],
                        "kernel_ms": {k: round(v, 4) for k, v in st["kernel_ms"].items() if v}}
-                      for st, (p, mode) in zip(all_stats[-len(runs):], runs)],
+                      for st, (p, mode) in zip(per_query_stats, runs)],
         "roofline": roofline,
     }
     out.update(extra)

@@ -127,6 +127,11 @@ typedef struct {
                                  result, used to check that reordering does not  \
                                  change it. */
 #define HPM_F_TIMING 0x2u     /* record per-phase device times (hpm_last_stats) */
+/* With HPM_F_TIMING: record events only around the launches of the kernel
+ * families whose bit (1 << HPM_K_*) is set in mask; mask 0 = every family.
+ * Each timed launch costs two event records on the stream, so timing a few
+ * families disturbs the call less than timing all of them. */
+#define HPM_F_TIMING_KINDS(mask) ((((uint32_t)(mask)) & 0xffu) << 16)
 #define HPM_F_NO_FILTER 0x4u  /* do not pre-filter long shared candidate lists \
                                  (same result; for checking and measurement) */
 #define HPM_F_OVERLAP 0x8u    /* apply the edge validator's neighbour-overlap  \

@@ -1143,6 +1143,8 @@ __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan
   __shared__ long long s_scan[kWaves + 1];
   __shared__ int32_t s_iscan[kWaves + 1];
   __shared__ int32_t s_q[kBlock];
+  __shared__ int32_t s_len[kBlock], s_lst[kBlock];  // queued rows: list length and start
+  __shared__ int4 s_rng[kBlock];  // queued rows, one position in umask: its out / in ranges
   __shared__ int32_t s_list[kWaves * kCountStage];
   const int32_t a = d;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
@@ -1168,15 +1170,21 @@ __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan
           acc += cnt;
         } else {
           int64_t nbrs = 0;
+          int4 rng = make_int4(0, 0, 0, 0);
           for (int q = 0; q < d; ++q)
             if ((umask >> q) & 1u) {
               const int32_t f = row[q];
-              nbrs += (int64_t)(g.out_off[f + 1] - g.out_off[f]) + (g.in_off[f + 1] - g.in_off[f]);
+              rng = make_int4(g.out_off[f], g.out_off[f + 1], g.in_off[f], g.in_off[f + 1]);
+              nbrs += (int64_t)(rng.y - rng.x) + (rng.w - rng.z);
             }
-          if (nbrs <= kCountNbrMax)
+          if (nbrs <= kCountNbrMax) {
             queue = true;
-          else
+            s_len[threadIdx.x] = len;
+            s_lst[threadIdx.x] = pv.y;
+            s_rng[threadIdx.x] = rng;  // used when umask has one position
+          } else {
             left = len;
+          }
         }
       } else if (len > 0) {
         const int32_t b = pv.x >> 2;
@@ -1227,9 +1235,10 @@ __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan
     const int32_t qb = wave * nq / kWaves, qe = (wave + 1) * nq / kWaves;
     int32_t st_at = -1, st_len = -1;
     for (int32_t qi = qb; qi < qe; ++qi) {
-      const int64_t ri = i0 + s_q[qi];
-      const int32_t len = (int32_t)(off[ri + 1] - off[ri]);
-      const int32_t lst = piv[ri].y;
+      const int32_t t = s_q[qi];
+      const int64_t ri = i0 + t;
+      const int32_t len = s_len[t];
+      const int32_t lst = s_lst[t];
       const int32_t* row = rows + ri * d;
       const bool staged = len <= kCountStage;
       if (staged && (lst != st_at || len != st_len)) {
@@ -1244,18 +1253,23 @@ __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan
         const int32_t y = row[lane];
         if (staged ? lds_find(wl, len, y) >= 0 : find_in(fpool, lst, lst + len, y) >= 0) ++hits;
       }
+      const bool one = (umask & (umask - 1u)) == 0;
+      const int4 rng1 = s_rng[t];
       for (int q = 0; q < d; ++q) {
         if (!((umask >> q) & 1u)) continue;
-        const int32_t fq = row[q];
+        const int32_t fq = one ? 0 : row[q];
+        const int4 rq = one ? rng1
+                            : make_int4(g.out_off[fq], g.out_off[fq + 1], g.in_off[fq],
+                                        g.in_off[fq + 1]);
         for (int dir = 0; dir < 2; ++dir) {
           const int32_t* nb = dir ? g.in_nbrs : g.out_nbrs;
-          const int32_t lo = dir ? g.in_off[fq] : g.out_off[fq];
-          const int32_t hi = dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+          const int32_t lo = dir ? rq.z : rq.x;
+          const int32_t hi = dir ? rq.w : rq.y;
           for (int32_t x = lo + lane; x < hi; x += 64) {
             const int32_t y = nb[x];
             bool hit = staged ? lds_find(wl, len, y) >= 0 : find_in(fpool, lst, lst + len, y) >= 0;
             for (int p = 0; p < d && hit; ++p) hit = row[p] != y;
-            if (hit && dir) hit = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], y) < 0;
+            if (hit && dir) hit = find_in(g.out_nbrs, rq.x, rq.y, y) < 0;
             for (int q2 = 0; q2 < q && hit; ++q2) {
               if (!((umask >> q2) & 1u)) continue;
               const int32_t f2 = row[q2];

@@ -462,6 +462,7 @@ struct Matcher {
   bool timing;
   bool filter;
   int max_grid;
+  uint32_t timed_kinds = 0xffu;  // families timed when timing (bit = HPM_K_*)
   int64_t cap2 = 0;     // depth-2 rows per arc chunk
   int64_t chunk = 0;    // rows per frontier chunk at depth >= 3
   uint64_t budget = 0;  // scratch limit of the call
@@ -517,12 +518,13 @@ struct Matcher {
   template <class L>
   void launch(int kind, L&& fn) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (timing) {
+    const bool timed = timing && ((timed_kinds >> kind) & 1u);
+    if (timed) {
       a = event();
       hip_check(hipEventRecord(a, stream), "hipEventRecord");
     }
     hip_check(fn(), "kernel launch");
-    if (timing) {
+    if (timed) {
       b = event();
       hip_check(hipEventRecord(b, stream), "hipEventRecord");
       pending.push_back({kind, a, b});
@@ -1301,6 +1303,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
 
     Matcher M{G, W, stream, G->view(), plan, k, mappings, mappings ? cap : 0,
               (flags & HPM_F_TIMING) != 0, (flags & HPM_F_NO_FILTER) == 0, max_grid};
+    M.timed_kinds = (flags >> 16) & 0xffu ? (flags >> 16) & 0xffu : 0xffu;
     M.cap2 = cap2;
     M.chunk = chunk;
     M.budget = budget;

@@ -23,6 +23,14 @@ F_NO_REORDER = 0x1
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
+
+
+def F_TIMING_KINDS(*names):
+    """Flag bits that limit F_TIMING to the named kernel families (KERNELS)."""
+    mask = 0
+    for n in names:
+        mask |= 1 << KERNELS.index(n)
+    return (mask & 0xFF) << 16
 MAX_K = 16
 KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand", "last_level",
            "reduce", "filter")

@@ -43,6 +43,9 @@ def test_struct_mirrors_match_the_header(tmp_path):
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
         for fname, _ in py._fields_:
             lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    # the timing-family flag bits, one family at a time
+    for i, kname in enumerate(hb.KERNELS):
+        lines.append(f'  printf("timing {kname} %u\\n", HPM_F_TIMING_KINDS(1u << {i}));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "probe.c"
     src.write_text("\n".join(lines) + "\n")
@@ -53,6 +56,9 @@ def test_struct_mirrors_match_the_header(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     for line in out.splitlines():
         cname, what, val = line.split()
+        if cname == "timing":
+            assert hb.F_TIMING_KINDS(what) == int(val), line
+            continue
         py = mirrors[cname]
         got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
         assert got == int(val), line
