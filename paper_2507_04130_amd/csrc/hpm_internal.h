@@ -194,25 +194,27 @@ hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t 
                                 unsigned long long* counters, hipStream_t stream);
 // Pieces per group (raw list length split into runs of plen entries):
 // pbase[0..nslots] = their exclusive prefix sums, pbase[nslots] = total;
-// bsum as for launch_scan_lengths; pslot[piece] = its group (total entries).
+// bsum as for launch_scan_lengths; pslot[piece] = its group and pdesc[piece]
+// = {list start, end, pivot code, representative row or pivot vertex}
+// (total entries each).
 hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t d,
                                 const int2* piv, int32_t nslots,
                                 const unsigned long long* slot_key, const int32_t* slot_rep,
                                 int32_t plen, int64_t* pbase, int64_t* bsum, int32_t* pslot,
-                                hipStream_t stream);
+                                int4* pdesc, hipStream_t stream);
 // One block per piece (grid >= pbase[nslots]; the blocks past it exit): the
 // filtered list of each group into pool + slot_region[s], its length into
 // fcount[s].  Groups of two or more pieces go through tmp (pool's size) and
 // a second kernel that closes the gaps; tmp may be NULL only when every group
-// is one piece.  pcnt / pslot hold grid entries (pslot from
-// launch_filter_pieces).
+// is one piece.  pcnt / pslot / pdesc hold grid entries (pslot and pdesc
+// from launch_filter_pieces).
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
                                int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
                                int32_t nslots, const int64_t* pbase, int32_t plen, int32_t grid,
                                const unsigned long long* slot_key, const int32_t* slot_rep,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
-                               hipStream_t stream);
+                               const int4* pdesc, hipStream_t stream);
 // New list lengths into len[0..r) (+ block sums), grouped rows redirected in
 // piv (code bit 1); a row whose images differ from its group's representative
 // stays as it is.

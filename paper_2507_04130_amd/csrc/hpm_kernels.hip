@@ -1593,30 +1593,24 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
                                                          int32_t* __restrict__ fcount,
                                                          int32_t* __restrict__ tmp,
                                                          int32_t* __restrict__ pcnt,
-                                                         const int32_t* __restrict__ pslot) {
+                                                         const int32_t* __restrict__ pslot,
+                                                         const int4* __restrict__ pdesc) {
   __shared__ int32_t s_scan[kWaves + 1];
   __shared__ int32_t s_f[kMaxK];
   __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
   __shared__ int32_t s_pool[kTilePool];
   __shared__ int32_t s_n;
   const int64_t blk = blockIdx.x;
+  // the group, its list range, pivot code and row (or pivot vertex) are read
+  // beside the total and used only below it
   const int64_t total = pbase[nslots];
-  const int32_t s = pslot[blk];  // read beside the total; used only below it
+  const int32_t s = pslot[blk];
+  const int4 pd = pdesc[blk];
   if (blk >= total) return;
-  const int64_t p0 = pbase[s];
-  const int64_t npieces = pbase[s + 1] - p0;
-  const int64_t piece = blk - p0;
   const int32_t d = a;
-  int32_t code, pv_v = 0;
-  int64_t i = 0;
-  if (rmask) {
-    i = slot_rep[s];
-    code = piv[i].x;
-  } else {
-    const unsigned long long key = slot_key[s];
-    pv_v = (int32_t)(key & 0xffffffffull);
-    code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
-  }
+  const int32_t code = pd.z;
+  const int64_t i = rmask ? pd.w : 0;
+  const int32_t pv_v = rmask ? 0 : pd.w;
   const int32_t b = code >> 2;
   const bool out_dir = (code & 1) != 0;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
@@ -1639,13 +1633,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
   }
   __syncthreads();
   const int32_t ncons = s_n;
-  const int32_t v = rmask ? s_f[b] : pv_v;
-  const int32_t v0 = out_dir ? g.out_off[v] : g.in_off[v];
-  const int32_t v1 = out_dir ? g.out_off[v + 1] : g.in_off[v + 1];
-  const int32_t lo = (int32_t)(v0 + piece * plen);
-  const int32_t hi = (int64_t)v1 - lo > plen ? lo + plen : v1;
+  const int32_t lo = pd.x, hi = pd.y;
   const int32_t* lst = out_dir ? g.out_nbrs : g.in_nbrs;
-  int32_t* dst = npieces == 1 ? pool + slot_region[s] : tmp + slot_region[s] + piece * plen;
+  const int64_t p0 = pbase[s];
+  const int64_t npieces = pbase[s + 1] - p0;
+  int32_t* dst = npieces == 1 ? pool + slot_region[s] : tmp + slot_region[s] + (blk - p0) * plen;
   int32_t run = 0;
   for (int32_t base = lo; base < hi; base += kExpandTile) {
     const int32_t end = base + kExpandTile < hi ? base + kExpandTile : hi;
@@ -1747,13 +1739,44 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
   }
 }
 
-// pslot[pbase[s] .. pbase[s + 1]) = s for every group s.
-__global__ __launch_bounds__(kBlock) void k_filter_map(int32_t nslots,
+// For every group s and each of its pieces j = pbase[s] .. pbase[s + 1]:
+// pslot[j] = s and pdesc[j] = {first list entry, end, pivot code,
+// representative row (rmask != 0) or pivot vertex}, so that a block of
+// k_filter_lists starts loading its piece after one dependent read.
+__global__ __launch_bounds__(kBlock) void k_filter_map(DevGraph g,
+                                                       const int32_t* __restrict__ rows,
+                                                       int32_t d,
+                                                       const int2* __restrict__ piv,
+                                                       int32_t nslots,
+                                                       const unsigned long long* __restrict__ slot_key,
+                                                       const int32_t* __restrict__ slot_rep,
+                                                       int32_t plen,
                                                        const int64_t* __restrict__ pbase,
-                                                       int32_t* __restrict__ pslot) {
+                                                       int32_t* __restrict__ pslot,
+                                                       int4* __restrict__ pdesc) {
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < nslots;
-       s += (int64_t)gridDim.x * kBlock)
-    for (int64_t j = pbase[s]; j < pbase[s + 1]; ++j) pslot[j] = (int32_t)s;
+       s += (int64_t)gridDim.x * kBlock) {
+    int32_t v, code, who;
+    if (slot_rep) {
+      who = slot_rep[s];
+      code = piv[who].x;
+      v = rows[(int64_t)who * d + (code >> 2)];
+    } else {
+      const unsigned long long key = slot_key[s];
+      v = (int32_t)(key & 0xffffffffull);
+      code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+      who = v;
+    }
+    const int32_t v0 = (code & 1) ? g.out_off[v] : g.in_off[v];
+    const int32_t v1 = (code & 1) ? g.out_off[v + 1] : g.in_off[v + 1];
+    int32_t lo = v0;
+    for (int64_t j = pbase[s]; j < pbase[s + 1]; ++j) {
+      const int32_t hi = (int64_t)v1 - lo > plen ? lo + plen : v1;
+      pslot[j] = (int32_t)s;
+      pdesc[j] = make_int4(lo, hi, code, who);
+      lo = hi;
+    }
+  }
 }
 
 // Pieces of groups with two or more: each block takes kMergePieces pieces;
@@ -2125,7 +2148,7 @@ hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t 
                                 const int2* piv, int32_t nslots,
                                 const unsigned long long* slot_key, const int32_t* slot_rep,
                                 int32_t plen, int64_t* pbase, int64_t* bsum, int32_t* pslot,
-                                hipStream_t stream) {
+                                int4* pdesc, hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   const int nb = (int)(((int64_t)nslots + kPivotTile - 1) / kPivotTile);
   k_filter_pieces<<<nb, kBlock, 0, stream>>>(g, rows, d, piv, nslots, slot_key, slot_rep, plen,
@@ -2134,8 +2157,8 @@ hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t 
   if (e != hipSuccess) return e;
   e = launch_scan_lengths(pbase, nslots, bsum, stream);
   if (e != hipSuccess) return e;
-  k_filter_map<<<grid_for(nslots, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(nslots, pbase,
-                                                                              pslot);
+  k_filter_map<<<grid_for(nslots, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+      g, rows, d, piv, nslots, slot_key, slot_rep, plen, pbase, pslot, pdesc);
   return hipGetLastError();
 }
 
@@ -2145,11 +2168,11 @@ hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uin
                                const unsigned long long* slot_key, const int32_t* slot_rep,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
-                               hipStream_t stream) {
+                               const int4* pdesc, hipStream_t stream) {
   if (nslots <= 0 || grid <= 0) return hipSuccess;
   k_filter_lists<<<grid, kBlock, 0, stream>>>(g, plan, abits, a, rows, piv, rmask, nslots, pbase,
                                               plen, slot_key, slot_rep, slot_region, pool, fcount,
-                                              tmp, pcnt, pslot);
+                                              tmp, pcnt, pslot, pdesc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tmp == nullptr) return e;
   k_filter_merge<<<(grid + kMergePieces - 1) / kMergePieces, kBlock, 0, stream>>>(

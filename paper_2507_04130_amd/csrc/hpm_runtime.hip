@@ -109,7 +109,7 @@ struct Workspace {
   DevBuf fkeys, frep, fdense, fslot_key, fslot_rep, fslot_region, fcount;
   // the filter's pieces: per-group prefix sums, per-piece counts and groups,
   // and the staging area of groups split over several blocks
-  DevBuf fpbase, fpbsum, fpcnt, fpslot, ftmp;
+  DevBuf fpbase, fpbsum, fpcnt, fpslot, fpdesc, ftmp;
   // count pass: list lengths left to the tiled last level, and their block sums
   DevBuf crest, cbsum;
   // per depth: prefix sums of short-row lengths and of long-row tile counts
@@ -127,7 +127,7 @@ struct Workspace {
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
                fslot_region.bytes + fcount.bytes + fpbase.bytes + fpbsum.bytes + fpcnt.bytes +
-               fpslot.bytes + ftmp.bytes + crest.bytes + cbsum.bytes;
+               fpslot.bytes + fpdesc.bytes + ftmp.bytes + crest.bytes + cbsum.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
            off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
@@ -139,7 +139,8 @@ struct Workspace {
     fkeys.release(); frep.release(); fdense.release(); fslot_key.release(); fslot_rep.release();
     fslot_region.release();
     fcount.release();
-    fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); ftmp.release();
+    fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); fpdesc.release();
+    ftmp.release();
     crest.release(); cbsum.release();
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
@@ -684,11 +685,14 @@ struct Matcher {
     uint64_t more = extra(W->fpool[d], (size_t)std::max<int64_t>(pool, 1) * 4) +
                     extra(W->fcount, (size_t)nslots * 4) +
                     extra(W->off2[d], (size_t)(r + 1) * 8) +
-                    extra(W->fpbase, (size_t)(nslots + 1) * 8) + extra(W->fpbsum, (size_t)nbs * 8);
+                    extra(W->fpbase, (size_t)(nslots + 1) * 8) + extra(W->fpbsum, (size_t)nbs * 8) +
+                    extra(W->fpcnt, (size_t)nslots * 4) + extra(W->fpslot, (size_t)nslots * 4) +
+                    extra(W->fpdesc, (size_t)nslots * 16);
     if (planned + more > budget) return;
     const uint64_t split_more = extra(W->ftmp, (size_t)std::max<int64_t>(pool, 1) * 4) +
                                 extra(W->fpcnt, (size_t)grid_split * 4) +
-                                extra(W->fpslot, (size_t)grid_split * 4);
+                                extra(W->fpslot, (size_t)grid_split * 4) +
+                                extra(W->fpdesc, (size_t)grid_split * 16);
     const bool split = grid_split > nslots && grid_split < INT32_MAX &&
                        planned + more + split_more <= budget;
     const int32_t plen = split ? hpm::kFilterPiece : INT32_MAX;
@@ -700,6 +704,7 @@ struct Matcher {
     need(W->fpbsum, (size_t)nbs * 8);
     need(W->fpcnt, (size_t)grid * 4);
     need(W->fpslot, (size_t)grid * 4);
+    need(W->fpdesc, (size_t)grid * 16);
     if (split) need(W->ftmp, (size_t)std::max<int64_t>(pool, 1) * 4);
     int64_t* off2 = W->off2[d].as<int64_t>();
     const unsigned long long* skey = W->fslot_key.as<unsigned long long>();
@@ -707,7 +712,7 @@ struct Matcher {
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_pieces(g, rows, d, piv, (int32_t)nslots, skey, srep, plen,
                                        W->fpbase.as<int64_t>(), W->fpbsum.as<int64_t>(),
-                                       W->fpslot.as<int32_t>(), stream);
+                                       W->fpslot.as<int32_t>(), W->fpdesc.as<int4>(), stream);
     });
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_lists(g, dplan(), bits(d), d, rows, piv, use_mask,
@@ -715,7 +720,8 @@ struct Matcher {
                                       (int32_t)grid, skey, srep, W->fslot_region.as<int64_t>(),
                                       W->fpool[d].as<int32_t>(), W->fcount.as<int32_t>(),
                                       split ? W->ftmp.as<int32_t>() : nullptr,
-                                      W->fpcnt.as<int32_t>(), W->fpslot.as<int32_t>(), stream);
+                                      W->fpcnt.as<int32_t>(), W->fpslot.as<int32_t>(),
+                                      W->fpdesc.as<int4>(), stream);
     });
     launch(HPM_K_FILTER, [&] {
       return hpm::launch_filter_apply(rows, (int32_t)r, d, piv, off, off2, hpm::kFilterMinLen,
