@@ -383,8 +383,8 @@ def main():
             log(f"warmup {i}: counts={counts}")
         # One step with events around every launch, before the timed region:
         # per-family times of the whole path, and the family that dominates.
-        # The timed steps then record events only around that family and the
-        # arc scan (two event records per timed launch cost the step time).
+        # The last timed step then records events only around that family and
+        # the arc scan (two event records per timed launch cost step time).
         _, prof_stats = step(hpm.F_TIMING)
         prof_ms = {}
         for st in prof_stats:
@@ -394,22 +394,23 @@ def main():
         dom_kind = max(costed_kinds, key=lambda k: prof_ms.get(k, 0.0))
         timed_flags = hpm.F_TIMING | hpm.F_TIMING_KINDS(dom_kind, "edge_scan")
         log(f"profile step: {({k: round(v, 3) for k, v in prof_ms.items() if v})}; "
-            f"timing {dom_kind} and edge_scan in the timed steps")
+            f"timing {dom_kind} and edge_scan in the last timed step")
         extra["kernel_ms_per_step_all_families"] = {k: round(v, 4) for k, v in prof_ms.items()}
         extra["kernel_ms_source"] = ("kernel_ms_per_step_all_families: one step with events "
                                      "around every launch, before the timed steps; "
-                                     "kernel_ms_per_step and roofline: the timed steps, "
+                                     "kernel_ms_per_step and roofline: the last timed step, "
                                      f"events around {dom_kind} and edge_scan only")
         torch.cuda.synchronize()
-        all_stats = []
         t_start = time.perf_counter()
         for i in range(args.steps):
-            counts, stats = step(timed_flags)
-            all_stats.extend(stats)
+            # events in the last timed step only: the family times and the
+            # roofline come from that step's launches
+            counts, stats = step(timed_flags if i == args.steps - 1 else 0)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         log(f"timed {args.steps} steps in {elapsed:.3f}s")
-        timed_steps = args.steps
+        all_stats = stats
+        timed_steps = 1
 
     per_query_stats = prof_stats if (not batch and not serve) else all_stats[-len(runs):]
     matches_per_step = sum(counts)
