@@ -360,6 +360,15 @@ def test_prefilter_split_over_pieces_changes_nothing():
         assert oracle.fingerprint(r1) == want.fingerprint
         say(f"hub filter {name}/{mode}: count={c1} lists={st['filtered_lists']} "
             f"pieces={st['filter_pieces']}")
+        # tight scratch budgets: chunked frontiers, and filters that run
+        # without the split staging area or not at all
+        for budget in (24 << 20, 6 << 20):
+            c2, r2 = gpu_rows(dg, p, mode, budget=budget)
+            st2 = hpm.last_stats()
+            say(f"  budget {budget >> 20} MiB: chunks={st2['chunks']} "
+                f"lists={st2['filtered_lists']} pieces={st2['filter_pieces']}")
+            assert c2 == c1
+            np.testing.assert_array_equal(r2, r1)
     assert pieces > lists > 0
 
 
