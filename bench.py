@@ -411,6 +411,22 @@ def main():
         log(f"timed {args.steps} steps in {elapsed:.3f}s")
         all_stats = stats
         timed_steps = 1
+        # For reference, outside the timed region: the same step's queries
+        # as one hpm_match_batch call (queries overlapped on worker streams,
+        # no events), counts checked against the sequential ones.
+        if len(runs) > 1:
+            bw = args.batch_workers or len(runs)
+            got, _ = hpm.match_batch(dg, pats, modes, workers=bw, stream=stream)
+            assert got == counts, "batched counts differ from the sequential ones"
+            torch.cuda.synchronize()
+            t_b = time.perf_counter()
+            for _ in range(args.steps):
+                hpm.match_batch(dg, pats, modes, workers=bw, stream=stream)
+            torch.cuda.synchronize()
+            b_s = (time.perf_counter() - t_b) / args.steps
+            extra["batched_step"] = {"workers": bw, "ms_per_step": round(1000.0 * b_s, 4),
+                                     "matches_per_sec": sum(counts) / b_s}
+            log(f"batched step ({bw} workers): {1000.0 * b_s:.3f} ms")
 
     per_query_stats = prof_stats if (not batch and not serve) else all_stats[-len(runs):]
     matches_per_step = sum(counts)
