@@ -239,8 +239,9 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the matcher shards by arc range across GPUs "
-              "only in design, and no multi-GPU run exists in this build.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: sharding the matcher by arc range across "
+              "GPUs is designed but not implemented, so there is no multi-GPU run.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
