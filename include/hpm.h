@@ -37,7 +37,8 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 2
+/* 3: hpm_match_stats.filter_pieces appended; HPM_F_TIMING_KINDS. */
+#define HPM_ABI_VERSION 3
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 

@@ -20,6 +20,7 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
+ABI_VERSION = 3  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
@@ -141,6 +142,12 @@ def load() -> ctypes.CDLL:
                  "hpm_server_read_stats", "hpm_server_destroy", "hpm_plan_order",
                  "hpm_last_stats"):
         getattr(lib, name).restype = ctypes.c_int
+    if lib.hpm_abi_version() != ABI_VERSION:
+        # the struct mirrors in this module follow this ABI; a stale build
+        # would write past them
+        raise ImportError(f"{LIB_PATH} implements ABI {lib.hpm_abi_version()}, this binding "
+                          f"expects {ABI_VERSION}: rebuild it with "
+                          "`python -m paper_2507_04130_amd.build`")
     _lib = lib
     return lib
 
