@@ -209,9 +209,8 @@ hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t 
 // is one piece.  pcnt / pslot / pdesc hold grid entries (pslot and pdesc
 // from launch_filter_pieces).
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
-                               int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
-                               int32_t nslots, const int64_t* pbase, int32_t plen, int32_t grid,
-                               const unsigned long long* slot_key, const int32_t* slot_rep,
+                               int32_t a, const int32_t* rows, uint32_t rmask, int32_t nslots,
+                               const int64_t* pbase, int32_t plen, int32_t grid,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
                                const int4* pdesc, hipStream_t stream);

@@ -1578,16 +1578,14 @@ __global__ __launch_bounds__(kBlock) void k_filter_pieces(DevGraph g,
 // one-piece group writes its list to pool + slot_region[s] and its length to
 // fcount[s]; a piece of a longer group writes to tmp at the piece's own
 // offset in the group's region, for k_filter_merge.  Every piece leaves its
-// count in pcnt; pslot[blk] names the block's group (k_filter_map).
+// count in pcnt; pslot[blk] names the block's group and pdesc[blk] its list
+// range, pivot code and row (k_filter_map).
 __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
                                                          const uint32_t* __restrict__ abits,
                                                          int32_t a, const int32_t* __restrict__ rows,
-                                                         const int2* __restrict__ piv,
                                                          uint32_t rmask, int32_t nslots,
                                                          const int64_t* __restrict__ pbase,
                                                          int32_t plen,
-                                                         const unsigned long long* __restrict__ slot_key,
-                                                         const int32_t* __restrict__ slot_rep,
                                                          const int64_t* __restrict__ slot_region,
                                                          int32_t* __restrict__ pool,
                                                          int32_t* __restrict__ fcount,
@@ -2163,16 +2161,14 @@ hipError_t launch_filter_pieces(const DevGraph& g, const int32_t* rows, int32_t 
 }
 
 hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uint32_t* abits,
-                               int32_t a, const int32_t* rows, const int2* piv, uint32_t rmask,
-                               int32_t nslots, const int64_t* pbase, int32_t plen, int32_t grid,
-                               const unsigned long long* slot_key, const int32_t* slot_rep,
+                               int32_t a, const int32_t* rows, uint32_t rmask, int32_t nslots,
+                               const int64_t* pbase, int32_t plen, int32_t grid,
                                const int64_t* slot_region, int32_t* pool, int32_t* fcount,
                                int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
                                const int4* pdesc, hipStream_t stream) {
   if (nslots <= 0 || grid <= 0) return hipSuccess;
-  k_filter_lists<<<grid, kBlock, 0, stream>>>(g, plan, abits, a, rows, piv, rmask, nslots, pbase,
-                                              plen, slot_key, slot_rep, slot_region, pool, fcount,
-                                              tmp, pcnt, pslot, pdesc);
+  k_filter_lists<<<grid, kBlock, 0, stream>>>(g, plan, abits, a, rows, rmask, nslots, pbase, plen,
+                                              slot_region, pool, fcount, tmp, pcnt, pslot, pdesc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tmp == nullptr) return e;
   k_filter_merge<<<(grid + kMergePieces - 1) / kMergePieces, kBlock, 0, stream>>>(

@@ -715,9 +715,9 @@ struct Matcher {
                                        W->fpslot.as<int32_t>(), W->fpdesc.as<int4>(), stream);
     });
     launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_lists(g, dplan(), bits(d), d, rows, piv, use_mask,
-                                      (int32_t)nslots, W->fpbase.as<int64_t>(), plen,
-                                      (int32_t)grid, skey, srep, W->fslot_region.as<int64_t>(),
+      return hpm::launch_filter_lists(g, dplan(), bits(d), d, rows, use_mask, (int32_t)nslots,
+                                      W->fpbase.as<int64_t>(), plen, (int32_t)grid,
+                                      W->fslot_region.as<int64_t>(),
                                       W->fpool[d].as<int32_t>(), W->fcount.as<int32_t>(),
                                       split ? W->ftmp.as<int32_t>() : nullptr,
                                       W->fpcnt.as<int32_t>(), W->fpslot.as<int32_t>(),
