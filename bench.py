@@ -232,6 +232,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: apply the neighbour-overlap test to depth-2 rows (HPM_F_OVERLAP)")
+    ap.add_argument("--batched-ref", type=int, default=1,
+                    help="also run the step's queries as one batched call (outside the "
+                         "timed region; 0 for hardware-counter runs)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -415,7 +418,7 @@ def main():
         # For reference, outside the timed region: the same step's queries
         # as one hpm_match_batch call (queries overlapped on worker streams,
         # no events), counts checked against the sequential ones.
-        if len(runs) > 1:
+        if len(runs) > 1 and args.batched_ref:
             bw = args.batch_workers or len(runs)
             got, _ = hpm.match_batch(dg, pats, modes, workers=bw, stream=stream)
             assert got == counts, "batched counts differ from the sequential ones"
