@@ -586,13 +586,15 @@ struct Matcher {
   }
 
   // Point rows whose pivot list has >= kFilterMinLen entries at a filtered copy
-  // of that list, one per group of rows (see launch_filter_keys).  With two or
-  // more positions related to the new one, rows are first grouped by the
-  // images of all of them (the filtered list then holds exactly the
-  // candidates that satisfy every relation with those positions); if those
-  // groups are not shared enough, by pivot list.  On success *offp / *fpool /
-  // *work describe the new candidate ranges and done[d] the relations the
-  // lists enforce; otherwise nothing changes.
+  // of that list, one per group of rows (launch_filter_insert and
+  // launch_filter_groups form the groups).  With two or more positions
+  // related to the new one, rows are first grouped by the images of all of
+  // them (the filtered list then holds exactly the candidates that satisfy
+  // every relation with those positions), and for induced isomorphism first
+  // by those plus every earlier position but the last; if those groups are
+  // not shared enough, by pivot list.  On success *offp / *fpool / *work
+  // describe the new candidate ranges and done[d] the relations the lists
+  // enforce; otherwise nothing changes.
   void filter_pivots(int32_t d, const int32_t* rows, int64_t r, int2* piv, const int64_t* off,
                      const int64_t** offp, const int32_t** fpool, int64_t* work) {
     const int64_t max_long = std::min<int64_t>(r, *work / hpm::kFilterMinLen);
