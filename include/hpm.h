@@ -327,7 +327,9 @@ enum {
 
 /* Per-call statistics of the calling thread's most recent successful hpm_match.
  * kernel_ms is filled only when HPM_F_TIMING was set (device time from HIP
- * events recorded around every launch on the caller's stream), else 0. */
+ * events recorded around every launch on the caller's stream, or around the
+ * launches of the families HPM_F_TIMING_KINDS selects), else 0;
+ * kernel_launches counts every launch either way. */
 typedef struct {
   uint64_t struct_size;          /* sizeof(hpm_match_stats)                           */
   uint64_t count;                /* embeddings                                        */
