@@ -172,6 +172,17 @@ struct Search {
     return true;
   }
 
+  // Pattern pair (a,b) at index ab = a*k+b against the target pair (u,v):
+  // a pattern arc needs the target arc with its predicate; a pattern non-arc
+  // needs a target non-arc under induced isomorphism and nothing otherwise.
+  bool pair_ok(int32_t ab, int32_t u, int32_t v) const {
+    int32_t arc = pl.arc_id[(size_t)ab];
+    if (arc < 0 && mode != MODE_ISO) return true;
+    int64_t eid = find_arc(g, u, v);
+    if (arc >= 0) return eid >= 0 && arc_ok(arc, eid);
+    return eid < 0;
+  }
+
   // Is target vertex c a consistent image for pattern vertex a at depth d?
   bool feasible(int32_t d, int32_t a, int32_t c) const {
     for (int32_t e = 0; e < d; ++e)
@@ -180,22 +191,9 @@ struct Search {
     for (int32_t e = 0; e < d; ++e) {
       int32_t b = pl.order[e];
       int32_t fb = f[b];
-      // direction b -> a
-      int32_t arc = pl.arc_id[(size_t)b * p.k + a];
-      int64_t eid = find_arc(g, fb, c);
-      if (arc >= 0) {
-        if (eid < 0 || !arc_ok(arc, eid)) return false;
-      } else if (mode == MODE_ISO && eid >= 0) {
-        return false;
-      }
-      // direction a -> b
-      arc = pl.arc_id[(size_t)a * p.k + b];
-      eid = find_arc(g, c, fb);
-      if (arc >= 0) {
-        if (eid < 0 || !arc_ok(arc, eid)) return false;
-      } else if (mode == MODE_ISO && eid >= 0) {
-        return false;
-      }
+      // direction b -> a, then a -> b; an absent pattern arc constrains the
+      // target only under induced isomorphism, so monomorphism skips its lookup
+      if (!pair_ok(b * p.k + a, fb, c) || !pair_ok(a * p.k + b, c, fb)) return false;
     }
     return true;
   }
