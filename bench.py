@@ -11,7 +11,14 @@ the roofline position of the dominant kernel (algorithmic bytes over its
 average launch time, from HIP events recorded around every launch on the
 stream it runs on), and the CPU oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload rmat20|er1k|chunglu]
+    python bench.py [--steps K] [--warmup W] [--workload chunglu|rmat20|er1k|batch256|serve]
+
+Default workload: the connectome-shaped graph (2e7 vertices, 1.5e8 arcs), the
+largest single-GPU configuration.  Before every timed step a scratch buffer of
+--flush-mib MiB (default 2048) is written, so that no part of the graph is left
+in the 256 MB last-level (infinity) cache by the previous step; each step is
+timed on its own between two device synchronisations, and the line reports the
+median, mean with a 95% confidence interval, and minimum of the step times.
 """
 from __future__ import annotations
 
@@ -158,6 +165,67 @@ def cpu_baseline(g, runs, seconds_target):
                       f"{found} matches in {secs:.1f} s"}
 
 
+def step_statistics(step_s):
+    """Median, mean with a 95% confidence interval (Student t), and minimum of
+    per-step wall times, in milliseconds."""
+    import numpy as np
+    from scipy import stats as sst
+    a = 1000.0 * np.asarray(step_s, dtype=np.float64)
+    out = {"median": round(float(np.median(a)), 4), "mean": round(float(a.mean()), 4),
+           "min": round(float(a.min()), 4), "max": round(float(a.max()), 4), "n": int(a.size)}
+    if a.size > 1:
+        half = float(sst.t.ppf(0.975, a.size - 1) * a.std(ddof=1) / np.sqrt(a.size))
+        out["ci95"] = [round(out["mean"] - half, 4), round(out["mean"] + half, 4)]
+    return out
+
+
+def stream_peaks(torch, mib=4096, reps=5):
+    """Device-memory rates on this GPU over a buffer far larger than the
+    last-level cache, in GB/s of bytes moved, the best of `reps` runs each,
+    timed with HIP events on the current stream: read-only (the probe
+    library's streaming kernel, 16-byte non-temporal loads, at two grid
+    sizes), write-only (torch fill) and copy (torch copy, read + write)."""
+    import ctypes
+    n = mib << 18
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    nbytes = 4 * n
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2507_04130_amd", "libhpm_probe.so"))
+    lib.hpm_probe_read.restype = ctypes.c_int
+    lib.hpm_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+    sink = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def read(blocks):
+        def fn():
+            rc = lib.hpm_probe_read(a.data_ptr(), nbytes, blocks, stream, sink.data_ptr())
+            assert rc == 0, rc
+        return fn
+
+    out = {"buffer_mib": mib}
+    for name, fn, moved in (("read_2048_blocks", read(2048), nbytes),
+                            ("read_16384_blocks", read(16384), nbytes),
+                            ("write", lambda: b.fill_(2), nbytes),
+                            ("copy", lambda: b.copy_(a), 2 * nbytes)):
+        fn()
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[f"{name}_gbs"] = round(moved / (best / 1000.0) / 1e9, 1)
+    out["read_gbs"] = max(out["read_2048_blocks_gbs"], out["read_16384_blocks_gbs"])
+    del a, b, sink
+    torch.cuda.empty_cache()
+    return out
+
+
 def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
     """Replay one seeded Poisson trace; latency is result time minus scheduled
     arrival.  kind "served": every query is submitted to an hpm_server at its
@@ -218,9 +286,12 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20",
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--flush-mib", type=int, default=2048,
+                    help="scratch MiB written before every timed step (last-level cache "
+                         "flush); 0 = none")
+    ap.add_argument("--workload", default="chunglu",
                     choices=["rmat20", "er1k", "chunglu", "batch256", "serve"])
     ap.add_argument("--batch-workers", type=int, default=0,
                     help="host threads / streams of the batched call (batch256); 0 = tuned")
@@ -268,6 +339,13 @@ def main():
     stream = torch.cuda.current_stream()
 
     extra_flags = hpm.F_OVERLAP if args.overlap else 0
+    flush_buf = (torch.empty(args.flush_mib << 18, dtype=torch.int32, device="cuda")
+                 if args.flush_mib else None)
+
+    def flush():
+        # overwrite the last-level cache with unrelated lines before a step
+        if flush_buf is not None:
+            flush_buf.fill_(1)
 
     def step(timing_flags):
         counts, stats = [], []
@@ -404,15 +482,19 @@ def main():
                                      "around every launch, before the timed steps; "
                                      "kernel_ms_per_step and roofline: the last timed step, "
                                      f"events around {dom_kind} and edge_scan only")
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
+        step_s = []
         for i in range(args.steps):
+            flush()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             # events in the last timed step only: the family times and the
             # roofline come from that step's launches
             counts, stats = step(timed_flags if i == args.steps - 1 else 0)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        log(f"timed {args.steps} steps in {elapsed:.3f}s")
+            torch.cuda.synchronize()
+            step_s.append(time.perf_counter() - t0)
+        elapsed = sum(step_s)
+        extra["step_ms"] = step_statistics(step_s)
+        log(f"timed {args.steps} steps in {elapsed:.3f}s: {extra['step_ms']}")
         all_stats = stats
         timed_steps = 1
         # For reference, outside the timed region: the same step's queries
@@ -456,11 +538,15 @@ def main():
     launches = fam_launch[dom]
     avg_ms = fam_ms[dom] / launches
     achieved = bytes_by[dom] / (fam_ms[dom] / 1000.0) / 1e9
+    peaks = stream_peaks(torch)
+    log(f"stream peaks: {peaks}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.workload, dom, launches / timed_steps),
                 "kernel": dom, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": int(bytes_by[dom] / launches)}
+                "algorithmic_bytes_per_launch": int(bytes_by[dom] / launches),
+                "frac_of_measured_read_peak": round(achieved / peaks["read_gbs"], 4),
+                "measured_peaks": peaks}
     scan_gbs = bytes_by["edge_scan"] / (scan_ms / 1000.0) / 1e9 if scan_ms > 0 else None
 
     out = {

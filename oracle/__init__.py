@@ -52,6 +52,10 @@ def _load():
                              ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
                              ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_uint64,
                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Result)]
+    lib.og_check_rows.restype = ctypes.c_int64
+    lib.og_check_rows.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, ctypes.c_int32, P,
+                                  ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P,
+                                  P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_uint64, P]
     lib.og_free.argtypes = [P]
     lib.og_sort_rows.argtypes = [P, ctypes.c_uint64, ctypes.c_int32]
     lib.og_fingerprint.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, P]
@@ -123,6 +127,27 @@ def match(g, p, mode: int, threads: int = 1, rows: bool = True, root_mask=None,
         lib.og_free(ctypes.cast(res.rows, ctypes.c_void_p))
     return OracleResult(int(res.count), (int(res.fp1), int(res.fp2)), out_rows, dt, nthr,
                         int(tested.value))
+
+
+def check_rows(g, p, mode: int, rows: np.ndarray, threads: int = 1) -> np.ndarray:
+    """uint8 flag per row of an int32 [count, k] array (original pattern ids):
+    1 when the row is an embedding of p in g under `mode`, 0 otherwise."""
+    lib = _load()
+    out_off = np.ascontiguousarray(g.out_off, dtype=np.int64)
+    in_off = np.ascontiguousarray(g.in_off, dtype=np.int64)
+    out_nbrs, in_nbrs = _c32(g.out_nbrs), _c32(g.in_nbrs)
+    nv, ne = len(g.vcols), len(g.ecols)
+    vcols = _c32(np.stack(g.vcols)) if nv else np.zeros(1, np.int32)
+    ecols = _c32(np.stack(g.ecols)) if ne else np.zeros(1, np.int32)
+    r = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, p.k)
+    ok = np.zeros(r.shape[0], dtype=np.uint8)
+    rc = lib.og_check_rows(g.n, g.m, _p(out_off), _p(out_nbrs), _p(in_off), _p(in_nbrs), nv,
+                           _p(vcols), ne, _p(ecols), p.k, p.n_arcs, _p(_c32(p.src)),
+                           _p(_c32(p.dst)), _p(_c32(p.vop)), _p(_c32(p.vval)), _p(_c32(p.eop)),
+                           _p(_c32(p.eval)), int(mode), int(threads), _p(r), r.shape[0], _p(ok))
+    if rc < 0:
+        raise RuntimeError("og_check_rows failed")
+    return ok
 
 
 def sort_rows(rows: np.ndarray) -> np.ndarray:

@@ -340,6 +340,66 @@ int og_match(int32_t n, int64_t m, const int64_t* out_off, const int32_t* out_nb
   return 0;
 }
 
+// Membership test of given rows in the result set (the definition, Sec. II-A,
+// Eq. (1)-(3), applied to one complete map at a time): row i (original pattern
+// order) is an embedding when its images are pairwise distinct, every vertex
+// predicate holds, every pattern arc (a,b) has the target arc (f(a),f(b)) with
+// its predicate, and under induced isomorphism every other ordered pair maps to
+// a non-arc.  ok[i] receives 1 or 0; returns the number of rows that pass, or
+// -1 on bad arguments.
+int64_t og_check_rows(int32_t n, int64_t m, const int64_t* out_off, const int32_t* out_nbrs,
+                      const int64_t* in_off, const int32_t* in_nbrs, int32_t n_vcols,
+                      const int32_t* vcols, int32_t n_ecols, const int32_t* ecols, int32_t k,
+                      int32_t n_arcs, const int32_t* src, const int32_t* dst, const int32_t* vop,
+                      const int32_t* vval, const int32_t* eop, const int32_t* eval, int32_t mode,
+                      int32_t n_threads, const int32_t* rows, uint64_t count, uint8_t* ok) {
+  if (k < 1 || n < 0 || m < 0 || (count && (!rows || !ok))) return -1;
+  Graph g{n, m, out_off, out_nbrs, in_off, in_nbrs, n_vcols, vcols, n_ecols, ecols};
+  Pattern p{k, n_arcs, src, dst, vop, vval, eop, eval};
+  std::vector<int32_t> arc_id((size_t)k * k, -1);
+  for (int32_t i = 0; i < n_arcs; ++i) arc_id[(size_t)src[i] * k + dst[i]] = i;
+  if (n_threads <= 0) n_threads = omp_get_max_threads();
+  int64_t good = 0;
+#pragma omp parallel for num_threads(n_threads) schedule(static, 4096) reduction(+ : good)
+  for (int64_t i = 0; i < (int64_t)count; ++i) {
+    const int32_t* f = rows + (size_t)i * k;
+    bool pass = true;
+    for (int32_t a = 0; a < k && pass; ++a) {
+      if (f[a] < 0 || f[a] >= n) pass = false;
+      for (int32_t b = 0; b < a && pass; ++b)
+        if (f[a] == f[b]) pass = false;
+    }
+    for (int32_t a = 0; a < k && pass; ++a)
+      for (int32_t col = 0; col < n_vcols && pass; ++col)
+        if (!pred(vop[a * n_vcols + col], vval[a * n_vcols + col],
+                  vcols[(int64_t)col * n + f[a]]))
+          pass = false;
+    for (int32_t a = 0; a < k && pass; ++a)
+      for (int32_t b = 0; b < k && pass; ++b) {
+        if (a == b) continue;
+        const int32_t arc = arc_id[(size_t)a * k + b];
+        if (arc < 0 && mode != MODE_ISO) continue;
+        const int64_t eid = find_arc(g, f[a], f[b]);
+        if (arc < 0) {
+          pass = eid < 0;
+          continue;
+        }
+        if (eid < 0) {
+          pass = false;
+          continue;
+        }
+        for (int32_t col = 0; col < n_ecols && pass; ++col)
+          if (!pred(eop[arc * n_ecols + col], eval[arc * n_ecols + col],
+                    ecols[(int64_t)col * m + eid]))
+            pass = false;
+      }
+    ok[i] = pass ? 1 : 0;
+    good += pass ? 1 : 0;
+  }
+  (void)p;
+  return good;
+}
+
 void og_free(void* p) { std::free(p); }
 
 // Lexicographic in-place sort of [count][k] int32 rows.

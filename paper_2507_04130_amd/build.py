@@ -13,6 +13,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpm.so")
 SOURCES = ["hpm_kernels.hip", "hpm_runtime.hip"]
+# the benchmark's memory-read probe, a library of its own
+PROBE_LIB = os.path.join(HERE, "libhpm_probe.so")
+PROBE_SOURCES = ["hpm_probe.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -29,19 +32,24 @@ def hipcc() -> str:
     return path if os.path.exists(path) else "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2507_04130_amd/libhpm.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
+def _compile(lib: str, sources, verbose: bool) -> str:
+    tmp = lib + ".tmp"
     cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+           *[os.path.join(CSRC, s) for s in sources]]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libhpm.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libhpm.so and the benchmark's probe library (always rebuilds)."""
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _compile(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

@@ -418,25 +418,24 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
   for (int64_t t = t_begin; t < t_end; t += t_step) {
     const int64_t tb = e_begin + t * kTile;
     // All streamed arrays of the tile (tails, heads, the first constrained arc
-    // column, reverse-arc ids) are loaded before the first barrier, so the
-    // tile pays one HBM round trip; the flag tests follow from LDS and L2.
-    int32_t v0s[ITEMS], v1s[ITEMS], ev[ITEMS], rv[ITEMS];
+    // column) are loaded before the first barrier, so the tile pays one HBM
+    // round trip; the flag tests follow from LDS and L2.  Reverse-arc ids are
+    // gathered for the arcs that pass every other test only.
+    int32_t v0s[ITEMS], v1s[ITEMS], ev[ITEMS];
     uint32_t valid = 0;
 #pragma unroll
     for (int iv = 0; iv < ITEMS / 4; ++iv) {
       const int64_t e0 = tb + ((int64_t)iv * kBlock + threadIdx.x) * 4;
-      int32_t xs[4], ys[4], es[4], rs[4];
+      int32_t xs[4], ys[4], es[4];
       if (e0 + 4 <= e_end) {
         // streamed once: non-temporal, so the flag bitmaps stay in L2
         const v4i a = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(g.src + e0));
         const v4i b = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(g.out_nbrs + e0));
-        v4i c = {0, 0, 0, 0}, r = {-1, -1, -1, -1};
+        v4i c = {0, 0, 0, 0};
         if (ec0 >= 0) c = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(ecol0 + e0));
-        if (rev) r = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(g.rev_eid + e0));
         xs[0] = a.x; xs[1] = a.y; xs[2] = a.z; xs[3] = a.w;
         ys[0] = b.x; ys[1] = b.y; ys[2] = b.z; ys[3] = b.w;
         es[0] = c.x; es[1] = c.y; es[2] = c.z; es[3] = c.w;
-        rs[0] = r.x; rs[1] = r.y; rs[2] = r.z; rs[3] = r.w;
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -444,7 +443,6 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
           xs[j] = in ? g.src[e0 + j] : g.src[tb];  // padding stays in the tail window
           ys[j] = in ? g.out_nbrs[e0 + j] : 0;
           es[j] = (in && ec0 >= 0) ? ecol0[e0 + j] : 0;
-          rs[j] = (in && rev) ? g.rev_eid[e0 + j] : -1;
         }
       }
 #pragma unroll
@@ -452,7 +450,6 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
         v0s[iv * 4 + j] = fwd ? xs[j] : ys[j];
         v1s[iv * 4 + j] = fwd ? ys[j] : xs[j];
         ev[iv * 4 + j] = es[j];
-        rv[iv * 4 + j] = rs[j];
         valid |= (uint32_t)(e0 + j < e_end) << (iv * 4 + j);
       }
     }
@@ -515,7 +512,14 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan(DevGraph g, const DevPlan*
       }
     }
     if (rev && keep) {
-      // the reverse arc y -> x of each scanned arc, from the streamed id array
+      // the reverse arc y -> x of each surviving arc: its id gathered from the
+      // reverse-arc index (all loads issued before any is used)
+      int32_t rv[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int64_t e = tb + ((int64_t)(i >> 2) * kBlock + threadIdx.x) * 4 + (i & 3);
+        rv[i] = ((keep >> i) & 1u) ? g.rev_eid[e] : -1;
+      }
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         if (!((keep >> i) & 1u)) continue;

@@ -158,3 +158,34 @@ def all_supergraphs(k, arcs):
     for r in range(len(rest) + 1):
         for extra in itertools.combinations(rest, r):
             yield sorted(base) + list(extra)
+
+
+def bipartite_k2_mono(g, s, target_labels, arc_ge):
+    """Monomorphisms of the complete bipartite pattern with s sources and two
+    targets (every source -> both targets), sources unlabelled, target t
+    (t = 0, 1) restricted to vertex label target_labels[t] on column 0 (None:
+    any), every arc GE arc_ge on arc column 0.
+
+    Writing c(y, z) for the number of common in-neighbours x of y and z whose
+    arcs x->y and x->z both pass the arc predicate, the count is the sum over
+    ordered pairs y != z of admissible targets of the falling factorial
+    c(y, z) (c(y, z) - 1) ... (c(y, z) - s + 1): the s sources are distinct
+    common in-neighbours, and they differ from y and z because the graph has
+    no self-loops.  c is the sparse product B_y^T B_z of the filtered
+    adjacency restricted to each target's admissible columns.
+    """
+    import scipy.sparse as sp
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.out_off))
+    ok = np.asarray(g.ecols[0]) >= arc_ge
+    A = sp.csc_matrix((np.ones(int(ok.sum()), dtype=np.int64), (src[ok], g.out_nbrs[ok])),
+                      shape=(g.n, g.n))
+    lab = np.asarray(g.vcols[0])
+    cols = [np.flatnonzero(lab == t) if t is not None else np.arange(g.n) for t in target_labels]
+    C = (A[:, cols[0]].T @ A[:, cols[1]]).tocoo()
+    c = C.data.astype(np.int64)
+    keep = cols[0][C.row] != cols[1][C.col]
+    c = c[keep]
+    total = np.ones_like(c)
+    for i in range(s):
+        total = total * (c - i)
+    return int(total.sum())

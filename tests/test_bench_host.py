@@ -68,3 +68,13 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
+
+
+def test_step_statistics():
+    st = bench.step_statistics([0.010, 0.012, 0.011, 0.013, 0.009])
+    assert st["median"] == 11.0 and st["min"] == 9.0 and st["max"] == 13.0 and st["n"] == 5
+    assert abs(st["mean"] - 11.0) < 1e-9
+    lo, hi = st["ci95"]
+    # t(0.975, 4) = 2.776, s = 1.5811 ms, half width = 2.776 * 1.5811 / sqrt(5)
+    assert abs((hi - lo) / 2 - 2.776445 * 1.581139 / 5 ** 0.5) < 1e-3
+    assert "ci95" not in bench.step_statistics([0.5])

@@ -1,14 +1,19 @@
 """Parity on the full connectome-shaped workload (2e7 vertices, ~1.5e8 arcs), GPU.
 
-The oracle cannot enumerate these queries in full within a test, so each is
-checked on samples and by properties that hold at any size:
+Every query's full result is pinned: the GPU's rows are all checked as
+embeddings (the oracle's row membership test, over every row), no row
+repeats, and their number equals |R| from a source independent of the GPU:
+the oracle's full count (tests/golden/c3_full.json, written by the committed
+screening script by root slices) and, for the bi-fan query, the closed-form
+sparse-product count.  Valid, distinct and |R| many means the row set is R.
+Where the oracle's run is complete, the fingerprint of all GPU rows equals the
+oracle's; for every finished root slice, the slice's count and fingerprint
+equal the oracle's.  Besides:
   * the rows whose image of pattern vertex 0 lies in a seeded 0.1% of the
     vertices equal, sorted and bit-exact, the oracle's rows for those roots;
-  * the GPU returns exactly `count` rows and no row twice;
-  * a seeded sample of 20,000 rows are embeddings: injective, labels and arc
-    weights satisfy the predicates, every pattern arc maps to a target arc;
   * a run with an 8 GiB scratch budget (chunked frontiers) gives the same count.
 """
+import json
 import os
 import sys
 
@@ -19,11 +24,24 @@ import oracle
 import paper_2507_04130_amd as hpm
 from synth import configs
 from synth.patterns import MONO
+from tests import pins
 
 # generating the graph and the oracle slices take minutes, not seconds
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 THREADS = min(16, len(os.sched_getaffinity(0)))
+
+
+def _full_results():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_full.json")
+    if not os.path.exists(path):
+        return {}, 1
+    with open(path) as f:
+        doc = json.load(f)
+    return doc["queries"], doc["slices"]
+
+
+FULL, FULL_SLICES = _full_results()
 
 
 def say(*a):
@@ -103,10 +121,37 @@ def test_connectome_query(connectome, qi):
     say(f"  oracle slice {sl.count} rows in {sl.seconds:.1f}s")
     mine = lexsorted(rows[key[rows[:, 0]]])
     np.testing.assert_array_equal(mine, sl.rows)
+    # every row is an embedding, and no row repeats
+    ok = oracle.check_rows(g, p, MONO, rows, threads=THREADS)
+    bad = np.flatnonzero(ok == 0)
+    assert bad.size == 0, f"{bad.size} rows are not embeddings, first {rows[bad[:4]]}"
     if cnt:
         pick = np.random.default_rng(5).integers(0, cnt, size=min(cnt, 20000))
         check_embeddings(g, p, rows[pick])
         assert_distinct(rows)
+    # |R| from sources independent of the GPU
+    pinned = 0
+    if p.name.startswith("bifan_plus1"):
+        s = p.k - 2
+        labels = tuple(int(p.vval[v, 0]) if p.vop[v, 0] == 1 else None for v in (s, s + 1))
+        cf = pins.bipartite_k2_mono(g, s, labels, int(p.eval[0, 0]))
+        say(f"  closed-form count {cf}")
+        assert cnt == cf
+        pinned += 1
+    full = FULL.get(p.name, {})
+    slices = full.get("slices", {})
+    if slices:
+        roots = rows[:, 0].astype(np.int64) % FULL_SLICES
+        for s_id, want in sorted(slices.items(), key=lambda kv: int(kv[0])):
+            part = rows[roots == int(s_id)]
+            assert part.shape[0] == want["count"], (p.name, s_id)
+            assert list(oracle.fingerprint(part)) == want["fingerprint"], (p.name, s_id)
+        say(f"  {len(slices)} of {FULL_SLICES} oracle root slices equal")
+    if "count" in full:
+        assert cnt == full["count"]
+        assert list(oracle.fingerprint(rows)) == full["fingerprint"]
+        pinned += 1
+    say(f"  full result pinned by {pinned} independent count(s)")
     c8, _ = hpm.match(dg, p, MONO, budget=8 << 30)
     assert c8 == cnt
 

@@ -231,3 +231,57 @@ def test_search_bound_on_complete_digraph(n, k, threads):
     assert not at.capped and at.count == full.count and at.tested == want
     below = oracle.match(g, p, MONO, threads=threads, rows=False, max_tested=want - 1)
     assert below.capped and below.count is None
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_row_check_equals_brute_force_membership(seed):
+    # every injective map (and some maps that repeat a vertex) is flagged
+    # exactly when brute-force enumeration lists it
+    import itertools
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(2, 7))
+    nv, ne = int(rng.integers(1, 3)), int(rng.integers(1, 3))
+    g = random_small_graph(rng, n, float(rng.uniform(0.2, 0.8)), nv, ne)
+    k = int(rng.integers(1, min(n, 4) + 1))
+    p = random_small_pattern(rng, k, nv, ne, connected=(seed % 4 != 0))
+    maps = np.array(list(itertools.permutations(range(n), k)), dtype=np.int32).reshape(-1, k)
+    if k >= 2:
+        rep = maps[: min(len(maps), 8)].copy()
+        rep[:, 1] = rep[:, 0]                 # not injective: never an embedding
+        maps = np.concatenate([maps, rep])
+    for mode in (ISO, MONO):
+        want = {tuple(r) for r in pins.brute(g, p, mode)}
+        flags = oracle.check_rows(g, p, mode, maps, threads=1 + seed % 3)
+        assert [tuple(r) in want for r in maps] == flags.astype(bool).tolist()
+
+
+def _bipartite_pattern(s, labels, thr):
+    from synth.patterns import make_pattern
+    k = s + 2
+    arcs = [(a, b) for a in range(s) for b in (s, s + 1)]
+    vpred = [[None] for _ in range(s)] + [[None if t is None else (EQ, t)] for t in labels]
+    return make_pattern(k, arcs, 1, 1, vpred, [[(GE, thr)]] * len(arcs), f"k{s}2")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_bipartite_closed_form_on_small_graphs(seed):
+    # the sparse-product count of complete bipartite patterns (s sources, two
+    # labelled targets) equals brute force on tiny graphs
+    rng = np.random.default_rng(77 + seed)
+    g = random_small_graph(rng, int(rng.integers(5, 8)), 0.6, 1, 1, nlab=2, nelab=3)
+    for s in (1, 2):
+        for labels in ((0, 1), (1, 1), (None, 0)):
+            p = _bipartite_pattern(s, labels, 1)
+            assert pins.bipartite_k2_mono(g, s, labels, 1) == pins.brute(g, p, MONO).shape[0]
+
+
+def test_bipartite_closed_form_equals_the_oracle_on_a_connectome_graph():
+    # the closed form that pins the full connectome bi-fan count, against the
+    # oracle on a scaled-down graph of the same generator
+    from synth import configs
+    g = configs.c3_graph(n=4_000, m=30_000)
+    for s, labels, thr in ((3, (3, 2), 2), (3, (None, 5), 6), (2, (1, 1), 3)):
+        p = _bipartite_pattern(s, labels, thr)
+        want = pins.bipartite_k2_mono(g, s, labels, thr)
+        got = oracle.match(g, p, MONO, threads=4, rows=False).count
+        assert got == want and want > 0, (s, labels, thr)
