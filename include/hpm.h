@@ -38,7 +38,8 @@ extern "C" {
 #endif
 
 /* 3: hpm_match_stats.filter_pieces appended; HPM_F_TIMING_KINDS. */
-#define HPM_ABI_VERSION 3
+/* 4: hpm_match_batch_persistent, hpm_batch_autotune, hpm_last_batch_stats. */
+#define HPM_ABI_VERSION 4
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -220,6 +221,102 @@ int hpm_match_batch(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
 int hpm_batch_tune(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
                    const int32_t* modes, void* stream, const hpm_match_opts* opts,
                    int32_t* best_workers, double* best_ms);
+
+/*
+ * The batched form as ONE persistent launch (Sec. IV-B: random patterns of
+ * many sizes against one graph).  One launch computes the vertex-validator
+ * bitmaps of every pattern; then the arc scan with state injection and the
+ * extension position by position run as tasks of a device work queue that
+ * one kernel of resident blocks drains: (pattern, arc range) scan tasks and
+ * (pattern, depth, chunk of partial mappings, candidate range) extension
+ * tasks, each pushing the tasks it creates.  No host round trip happens
+ * between depths or patterns.
+ *
+ * STATUS: switched off.  On the device the launch did not return (twice, on a
+ * batch of small patterns) and no cause has been shown, so both entry points
+ * below return HPM_E_UNSUPPORTED without launching anything; the batched form
+ * runs through hpm_match_batch.
+ *
+ * hpm_batch_config selects how the extension runs (hpm_batch_autotune picks
+ * it by timing the batch):
+ *   items_per_lane  candidates a lane holds per tile, 1, 2 or 4: the states a
+ *                   wavefront extends at once are 64 x items_per_lane
+ *   chunk_rows      partial mappings per task, 16..1024
+ *   task_work       candidates per task before its chunk is split into more
+ *                   tasks (>= 256; long hub lists spread over many blocks)
+ *   strategy        arc lookups: HPM_X_MAPPED binary-searches the mapped
+ *                   vertex's list (shared by a row's candidates);
+ *                   HPM_X_SHORTER searches the shorter of that list and the
+ *                   candidate's own list in the other direction
+ *   blocks_per_cu   resident blocks per compute unit (0 = as many as fit)
+ */
+#define HPM_X_MAPPED 0
+#define HPM_X_SHORTER 1
+
+typedef struct {
+  uint32_t struct_size;    /* sizeof(hpm_batch_config)                         */
+  int32_t items_per_lane;  /* 1, 2 or 4 (0 = 2)                                 */
+  int32_t chunk_rows;      /* 16..1024 (0 = 256)                                */
+  int32_t strategy;        /* HPM_X_MAPPED or HPM_X_SHORTER                     */
+  int64_t task_work;       /* >= 256 (0 = 16384)                                */
+  int32_t blocks_per_cu;   /* 0 = occupancy limit                              */
+  int32_t idle_us;         /* microseconds a block waits for a task before it  */
+                           /* leaves (0 = 1000); work left when all blocks have */
+                           /* left is drained by launching again               */
+} hpm_batch_config;
+
+/* Statistics of the calling thread's last hpm_match_batch_persistent. */
+typedef struct {
+  uint32_t struct_size;      /* sizeof(hpm_batch_stats)                         */
+  uint32_t error_bits;       /* 1 queue full, 2 a block left after waiting idle,   */
+                             /* 4 arena full, 8 a descriptor out of bounds      */
+  uint64_t tasks[4];         /* tasks run: [2] scan, [3] extension              */
+  int32_t launches;          /* persistent launches (1 unless blocks left idle)  */
+  int32_t reserved;
+  uint64_t queue_slots;      /* queue slots used                                 */
+  uint64_t arena_bytes;      /* partial-mapping bytes written                    */
+  uint64_t scratch_bytes;    /* device bytes the call held                       */
+  uint64_t fixed_bytes;      /* of the budget: queue, bitmaps, plans, results;   */
+                             /* the rest is the arena                           */
+  uint64_t arena_capacity;   /* arena bytes the launch could hand out            */
+  int32_t grid;              /* resident blocks of the launch                    */
+  int32_t fallback_patterns; /* patterns rerun with hpm_match (arena or queue full) */
+  double kernel_ms;          /* device time of the launch (HIP events)           */
+  double ms_total;           /* host wall time of the call                       */
+} hpm_batch_stats;
+
+/*
+ * hpm_match_batch_persistent -- counts of n patterns in one persistent launch.
+ * Arguments and results as hpm_match_batch (counts[i], status[i] for every
+ * i; counts only); cfg NULL = defaults.  opts->hbm_budget_bytes (0 = 25% of
+ * free device memory) bounds the call's scratch: the queue, the validator
+ * bitmaps and an arena that holds every partial mapping of the batch.  A
+ * pattern whose rows do not fit the arena (or tasks the queue) is finished
+ * with hpm_match on the same stream afterwards, so results never depend on
+ * the budget; hpm_batch_stats.fallback_patterns counts them.  opts with a
+ * max_matches limit or HPM_F_OVERLAP run every pattern through hpm_match.
+ * Returns HPM_OK or the status of the first failed pattern.  Errors:
+ * HPM_E_ARG, HPM_E_NOMEM (budget below queue + bitmaps), HPM_E_DEVICE, and
+ * per pattern the codes of hpm_match.
+ */
+int hpm_match_batch_persistent(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
+                               const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                               const hpm_batch_config* cfg, uint64_t* counts, int32_t* status);
+
+/*
+ * hpm_batch_autotune -- pick the hpm_batch_config for this batch on this
+ * graph: runs the batch once to warm up, then once per candidate
+ * configuration (items_per_lane x chunk_rows x task_work x strategy, 24
+ * settings), checks that every run gives the same counts, and returns the
+ * fastest (device time of the launch) in *best and its time in *best_ms
+ * (may be NULL).  Errors: as hpm_match_batch_persistent; HPM_E_ARG for an
+ * empty batch; HPM_E_INTERNAL if two settings disagree.
+ */
+int hpm_batch_autotune(const hpm_graph* g, int32_t n, const hpm_pattern* patterns,
+                       const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                       hpm_batch_config* best, double* best_ms);
+
+int hpm_last_batch_stats(hpm_batch_stats* out);
 
 /*
  * Serving: a resident graph answering a stream of queries.

@@ -6,5 +6,6 @@ thin ctypes binding.
 """
 from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_FILTER, F_NO_REORDER, F_OVERLAP, F_TIMING, F_TIMING_KINDS, Graph,  # noqa: F401
                   HpmError, Server,
-                  abi_version, batch_tune, last_stats, load, match, match_batch, plan_order,
-                  status_string)
+                  X_MAPPED, X_SHORTER, abi_version, batch_autotune, batch_tune,
+                  last_batch_stats, last_stats, load, match, match_batch, match_batch_persistent,
+                  plan_order, status_string)

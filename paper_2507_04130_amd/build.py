@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpm.so")
-SOURCES = ["hpm_kernels.hip", "hpm_runtime.hip"]
+SOURCES = ["hpm_kernels.hip", "hpm_persist.hip", "hpm_runtime.hip"]
 # the benchmark's memory-read probe, a library of its own
 PROBE_LIB = os.path.join(HERE, "libhpm_probe.so")
 PROBE_SOURCES = ["hpm_probe.hip"]

@@ -82,6 +82,74 @@ enum : uint32_t {
   kErrTranspose = 8u,    // in-CSR is not the transpose of the out-CSR
 };
 
+// ---- persistent batched matcher (hpm_persist.hip) ---------------------------------
+
+enum : int32_t { kTaskScan = 2, kTaskExpand = 3 };
+// launch state bits: queue full, a block left after waiting idle, arena
+// full, a descriptor outside the batch's bounds
+enum : uint32_t { kPErrQueueFull = 1u, kPErrIdleExit = 2u, kPErrArenaFull = 4u,
+                  kPErrBadTask = 8u };
+enum : uint32_t { kPatFailed = 1u, kPatOverflow = 2u };  // per-pattern flags
+enum : int32_t { kStratMapped = 0, kStratShorter = 1 };  // arc lookups of the extension
+
+// One work-queue slot.  ready is set last, after the descriptor is visible.
+struct alignas(64) PTask {
+  int32_t ready;
+  int32_t type;
+  int32_t q;      // pattern index in the batch
+  int32_t d;      // EXPAND: positions mapped in each row (the row width)
+  int32_t nrows;  // EXPAND: rows of the chunk
+  int32_t pad;
+  int64_t a;      // SCAN: first arc; EXPAND: arena offset of the rows
+  int64_t b;      // SCAN: end of the arc range
+  int64_t w0, w1; // EXPAND: candidate range of the chunk; w1 < 0: all of them
+};
+
+// Queue and arena state; the hot words sit on separate 128-byte lines.
+struct PState {
+  unsigned long long head;
+  unsigned long long pad0[15];
+  unsigned long long tail;
+  unsigned long long pad1[15];
+  unsigned long long pending;   // tasks queued or running
+  unsigned long long pad2[15];
+  unsigned long long arena_top; // int32 entries handed out
+  unsigned long long pad3[15];
+  uint32_t error;               // kPErr* bits
+  uint32_t pad4;
+  unsigned long long tasks[4];  // tasks run, by type
+};
+
+struct PParams {
+  DevGraph g;
+  const DevPlan* plans;       // [patterns]
+  uint32_t* bits;             // validator bitmaps: pattern q position p at bits + bit_base[q] + p * words
+  const int64_t* bit_base;    // [patterns]
+  int64_t words;              // uint32 words per bitmap
+  PTask* queue;
+  int64_t qcap;               // slots
+  int32_t* arena;
+  int64_t arena_cap;          // int32 entries
+  PState* st;
+  unsigned long long* counts; // [patterns]
+  uint32_t* pflags;           // [patterns] kPat* bits
+  int32_t n_pat;              // patterns of the batch
+  int32_t chunk_rows;         // rows per output chunk (at most 1024)
+  int64_t task_work;          // candidates per EXPAND task before the chunk is split
+  int32_t strategy;           // kStrat*
+  int64_t idle_ticks;         // wall-clock ticks a block waits for a task before it leaves
+};
+
+// Resident blocks per CU of the persistent kernel with `items` candidates per
+// lane (1, 2 or 4), 0 on error.
+int persist_blocks_per_cu(int items);
+hipError_t launch_persist(const PParams& P, int items, int grid, hipStream_t stream);
+// Validator bitmaps of every position of every pattern of a batch (pattern q
+// position p at bits + bit_base[q] + p * words; a plan with k = 0 writes none).
+hipError_t launch_batch_validate(const DevGraph& g, const DevPlan* plans, uint32_t* bits,
+                                 const int64_t* bit_base, int64_t words, int32_t n_pat,
+                                 hipStream_t stream);
+
 // ---- launchers (hpm_kernels.hip) -------------------------------------------------
 // Every launcher enqueues on `stream` and returns the launch status.
 

@@ -30,9 +30,19 @@ using hpm::DevGraph;
 using hpm::DevPlan;
 using hpm::kMaxCols;
 using hpm::kMaxK;
+using hpm::PParams;
+using hpm::PState;
+using hpm::PTask;
+using hpm::kPatFailed;
+using hpm::kPatOverflow;
+using hpm::kTaskScan;
+using hpm::launch_batch_validate;
+using hpm::launch_persist;
+using hpm::persist_blocks_per_cu;
 
 thread_local std::string t_error;
 thread_local hpm_match_stats t_stats;
+thread_local hpm_batch_stats t_bstats;
 
 struct Failure {
   int status;
@@ -150,6 +160,28 @@ struct Workspace {
   }
 };
 
+// Scratch of one persistent batched launch: plans, validator bitmaps, the
+// work queue, the row arena and per-pattern results.
+struct BatchSpace {
+  DevBuf plans, bits, bit_base, queue, arena, state, counts, pflags;
+  unsigned long long* host_counts = nullptr;  // pinned readback
+  uint32_t* host_flags = nullptr;
+  PState* host_state = nullptr;
+  size_t host_n = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~BatchSpace() {
+    if (host_counts) (void)hipHostFree(host_counts);
+    if (host_flags) (void)hipHostFree(host_flags);
+    if (host_state) (void)hipHostFree(host_state);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  size_t held() const {
+    return plans.bytes + bits.bytes + bit_base.bytes + queue.bytes + arena.bytes + state.bytes +
+           counts.bytes + pflags.bytes;
+  }
+};
+
 }  // namespace
 
 struct hpm_graph {
@@ -162,6 +194,7 @@ struct hpm_graph {
   DevBuf vcols[kMaxCols], ecols[kMaxCols], ecols_in[kMaxCols];
   std::mutex mu;
   std::vector<Workspace*> pool;
+  std::vector<BatchSpace*> bpool;  // scratch of persistent batched launches
   // Host-side statistics for frontier-size estimates (serving admission):
   // sorted evenly spaced samples of every attribute column and the
   // size-biased mean out- and in-degree (sum d^2 / sum d).
@@ -170,6 +203,7 @@ struct hpm_graph {
 
   ~hpm_graph() {
     for (Workspace* w : pool) delete w;
+    for (BatchSpace* b : bpool) delete b;
   }
   uint64_t bytes() const {
     uint64_t s = out_off.bytes + out_nbrs.bytes + in_off.bytes + in_nbrs.bytes + src.bytes +
@@ -1553,6 +1587,290 @@ void read_opts(const hpm_match_opts* opts, uint32_t* flags, uint64_t* budget, ui
   if (opts->struct_size >= sizeof(hpm_match_opts)) *limit = opts->max_matches;
 }
 
+// ------------------------------------------------------------ persistent batch
+
+// The persistent launch did not return on the device (twice, on a batch of
+// small patterns; its cause is not known), so its entry points refuse to run
+// it.  The code stays for the record and for a later investigation.
+constexpr bool kPersistentEnabled = false;
+
+// Arcs per scan task of the persistent launch; idle wait before a block
+// leaves; launches before the rest of a batch goes to the single-query path.
+constexpr int64_t kPScanArcs = 1 << 16;
+constexpr int32_t kPIdleUs = 1000;
+constexpr int kPMaxLaunches = 64;
+
+hpm_batch_config batch_defaults(const hpm_batch_config* cfg) {
+  hpm_batch_config c{};
+  c.struct_size = sizeof(hpm_batch_config);
+  c.items_per_lane = 2;
+  c.chunk_rows = 256;
+  c.strategy = HPM_X_MAPPED;
+  c.task_work = 16384;
+  c.blocks_per_cu = 0;
+  if (!cfg) return c;
+  if (cfg->struct_size < sizeof(hpm_batch_config)) fail(HPM_E_ARG, "cfg.struct_size too small");
+  if (cfg->items_per_lane) c.items_per_lane = cfg->items_per_lane;
+  if (cfg->chunk_rows) c.chunk_rows = cfg->chunk_rows;
+  c.strategy = cfg->strategy;
+  if (cfg->task_work) c.task_work = cfg->task_work;
+  c.blocks_per_cu = cfg->blocks_per_cu;
+  c.idle_us = cfg->idle_us;
+  if (c.items_per_lane != 1 && c.items_per_lane != 2 && c.items_per_lane != 4)
+    fail(HPM_E_ARG, "items_per_lane must be 1, 2 or 4");
+  if (c.chunk_rows < 16 || c.chunk_rows > 1024) fail(HPM_E_ARG, "chunk_rows must be 16..1024");
+  if (c.strategy != HPM_X_MAPPED && c.strategy != HPM_X_SHORTER) fail(HPM_E_ARG, "bad strategy");
+  if (c.task_work < 256) fail(HPM_E_ARG, "task_work must be >= 256");
+  if (c.blocks_per_cu < 0) fail(HPM_E_ARG, "blocks_per_cu must be >= 0");
+  if (c.idle_us < 0) fail(HPM_E_ARG, "idle_us must be >= 0");
+  return c;
+}
+
+// One persistent launch over the patterns that pass validation; throws
+// Failure for call-level errors.  Patterns the launch could not finish
+// (arena or queue full) are left with status HPM_E_NOMEM and need[i] = true
+// for the caller to rerun.
+void run_persistent(hpm_graph* G, int32_t n, const hpm_pattern* patterns, const int32_t* modes,
+                    hipStream_t stream, uint32_t flags, uint64_t budget,
+                    const hpm_batch_config& cfg, uint64_t* counts, int32_t* status,
+                    std::vector<std::string>& errors, std::vector<char>& need,
+                    hpm_batch_stats& bst) {
+  const int64_t words = (G->n + 63) / 64 * 2;
+  std::vector<DevPlan> plans((size_t)n);  // zero (k = 0) for rejected patterns
+  std::vector<int64_t> base((size_t)n, 0);
+  std::vector<PTask> seeds;
+  int64_t bit_words = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    counts[i] = 0;
+    need[i] = 0;
+    try {
+      if (modes[i] != HPM_ISO && modes[i] != HPM_MONO)
+        fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
+      PatternInfo info = check_pattern(&patterns[i], G->n_vcols, G->n_ecols);
+      std::vector<int32_t> order = plan_order(info, flags);
+      plans[i] = build_dev_plan(&patterns[i], info, order, G->n_vcols, G->n_ecols, modes[i]);
+      status[i] = HPM_OK;
+    } catch (const Failure& f) {
+      status[i] = f.status;
+      errors[i] = f.msg;
+      continue;
+    }
+    base[i] = bit_words;
+    bit_words += (words * plans[i].k + 63) / 64 * 64;  // 256-byte aligned per pattern
+    for (int64_t e = 0; e < G->m; e += kPScanArcs) {
+      PTask t{};
+      t.ready = 1;
+      t.type = kTaskScan;
+      t.q = i;
+      t.a = e;
+      t.b = std::min<int64_t>(e + kPScanArcs, G->m);
+      seeds.push_back(t);
+    }
+  }
+  // no arcs: every pattern (at least one arc) has no embedding
+  if (seeds.empty()) return;
+
+  BatchSpace* B = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(G->mu);
+    if (!G->bpool.empty()) {
+      B = G->bpool.back();
+      G->bpool.pop_back();
+    }
+  }
+  if (!B) B = new BatchSpace();
+  struct Return {
+    hpm_graph* G;
+    BatchSpace* B;
+    ~Return() {
+      std::lock_guard<std::mutex> lk(G->mu);
+      G->bpool.push_back(B);
+    }
+  } ret{G, B};
+
+  // queue: the seeds plus room for as many extension tasks again and more
+  const int64_t qcap = std::min<int64_t>(
+      std::max<int64_t>(2 * (int64_t)seeds.size() + (1 << 18), 1 << 18), int64_t(1) << 24);
+  if ((int64_t)seeds.size() > qcap) fail(HPM_E_NOMEM, "batch has more scan tasks than queue slots");
+  const uint64_t fixed = (uint64_t)n * (sizeof(DevPlan) + 8 + 8 + 4) + (uint64_t)bit_words * 4 +
+                         (uint64_t)qcap * sizeof(PTask) + sizeof(PState);
+  if (budget < fixed + (1u << 20))
+    fail(HPM_E_NOMEM, "scratch budget below the queue, bitmaps and a 1 MiB arena");
+  int64_t arena_ints = (int64_t)((budget - fixed) / 4);
+  arena_ints = std::min<int64_t>(arena_ints, int64_t(1) << 33);  // 32 GiB
+  if (B->held() > 2 * budget) {
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    B->plans.release(); B->bits.release(); B->bit_base.release(); B->queue.release();
+    B->arena.release(); B->state.release(); B->counts.release(); B->pflags.release();
+  }
+  B->plans.ensure((size_t)n * sizeof(DevPlan), stream);
+  B->bits.ensure((size_t)std::max<int64_t>(bit_words, 1) * 4, stream);
+  B->bit_base.ensure((size_t)n * 8, stream);
+  B->queue.ensure((size_t)qcap * sizeof(PTask), stream);
+  B->state.ensure(sizeof(PState), stream);
+  B->counts.ensure((size_t)n * 8, stream);
+  B->pflags.ensure((size_t)n * 4, stream);
+  B->arena.ensure((size_t)arena_ints * 4, stream);
+  if (B->host_n < (size_t)n) {
+    if (B->host_counts) (void)hipHostFree(B->host_counts);
+    if (B->host_flags) (void)hipHostFree(B->host_flags);
+    B->host_counts = nullptr;
+    B->host_flags = nullptr;
+    hip_check(hipHostMalloc((void**)&B->host_counts, (size_t)n * 8), "hipHostMalloc");
+    hip_check(hipHostMalloc((void**)&B->host_flags, (size_t)n * 4), "hipHostMalloc");
+    B->host_n = (size_t)n;
+  }
+  if (!B->host_state)
+    hip_check(hipHostMalloc((void**)&B->host_state, sizeof(PState)), "hipHostMalloc");
+  for (hipEvent_t& e : B->ev)
+    if (!e) hip_check(hipEventCreate(&e), "hipEventCreate");
+  int clock_khz = 0;
+  hip_check(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, G->device),
+            "hipDeviceGetAttribute");
+  if (clock_khz <= 0) clock_khz = 100000;
+
+  hip_check(hipMemcpyAsync(B->plans.p, plans.data(), (size_t)n * sizeof(DevPlan),
+                           hipMemcpyHostToDevice, stream), "upload");
+  hip_check(hipMemcpyAsync(B->bit_base.p, base.data(), (size_t)n * 8, hipMemcpyHostToDevice,
+                           stream), "upload");
+  hip_check(hipMemsetAsync(B->counts.p, 0, (size_t)n * 8, stream), "memset");
+  hip_check(hipMemsetAsync(B->pflags.p, 0, (size_t)n * 4, stream), "memset");
+  // queue slots past the seeds start not ready
+  hip_check(hipMemsetAsync(B->queue.p, 0, (size_t)qcap * sizeof(PTask), stream), "memset");
+  hip_check(hipMemcpyAsync(B->queue.p, seeds.data(), seeds.size() * sizeof(PTask),
+                           hipMemcpyHostToDevice, stream), "upload");
+  PState st0{};
+  st0.tail = seeds.size();
+  st0.pending = seeds.size();
+  hip_check(hipMemcpyAsync(B->state.p, &st0, sizeof(PState), hipMemcpyHostToDevice, stream),
+            "upload");
+
+  PParams P{};
+  P.g = G->view();
+  P.plans = B->plans.as<DevPlan>();
+  P.bits = B->bits.as<uint32_t>();
+  P.bit_base = B->bit_base.as<int64_t>();
+  P.words = words;
+  P.queue = B->queue.as<PTask>();
+  P.qcap = qcap;
+  P.arena = B->arena.as<int32_t>();
+  P.arena_cap = arena_ints;
+  P.st = B->state.as<PState>();
+  P.counts = B->counts.as<unsigned long long>();
+  P.pflags = B->pflags.as<uint32_t>();
+  P.n_pat = n;
+  P.chunk_rows = cfg.chunk_rows;
+  P.task_work = cfg.task_work;
+  P.strategy = cfg.strategy;
+  P.idle_ticks = (int64_t)clock_khz * (cfg.idle_us > 0 ? cfg.idle_us : kPIdleUs) / 1000;
+  int per_cu = persist_blocks_per_cu(cfg.items_per_lane);
+  if (per_cu <= 0) fail(HPM_E_DEVICE, "persistent kernel does not fit on a compute unit");
+  if (cfg.blocks_per_cu > 0) per_cu = std::min(per_cu, cfg.blocks_per_cu);
+  const int grid = per_cu * G->num_cus;
+  hip_check(hipEventRecord(B->ev[0], stream), "hipEventRecord");
+  hip_check(launch_batch_validate(P.g, P.plans, P.bits, P.bit_base, words, n, stream),
+            "validator launch");
+  // blocks leave after waiting idle; while tasks are left, launch again
+  int launches = 0;
+  for (;;) {
+    hip_check(launch_persist(P, cfg.items_per_lane, grid, stream), "persistent launch");
+    ++launches;
+    hip_check(hipMemcpyAsync(B->host_state, B->state.p, sizeof(PState), hipMemcpyDeviceToHost,
+                             stream), "readback");
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (B->host_state->pending == 0 || launches >= kPMaxLaunches) break;
+  }
+  hip_check(hipEventRecord(B->ev[1], stream), "hipEventRecord");
+  hip_check(hipMemcpyAsync(B->host_counts, B->counts.p, (size_t)n * 8, hipMemcpyDeviceToHost,
+                           stream), "readback");
+  hip_check(hipMemcpyAsync(B->host_flags, B->pflags.p, (size_t)n * 4, hipMemcpyDeviceToHost,
+                           stream), "readback");
+  hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, B->ev[0], B->ev[1]), "hipEventElapsedTime");
+  const PState& st = *B->host_state;
+  bst.kernel_ms = ms;
+  bst.error_bits = st.error;
+  bst.launches = launches;
+  for (int t = 0; t < 4; ++t) bst.tasks[t] = st.tasks[t];
+  bst.queue_slots = st.tail;
+  bst.arena_bytes = std::min<uint64_t>(st.arena_top, (uint64_t)arena_ints) * 4;
+  bst.scratch_bytes = B->held();
+  bst.fixed_bytes = fixed;
+  bst.arena_capacity = (uint64_t)arena_ints * 4;
+  bst.grid = grid;
+  // work left after the last launch: nothing of this batch is certain
+  const bool incomplete = st.pending != 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (status[i] != HPM_OK) continue;
+    const uint32_t f = B->host_flags[i];
+    if (incomplete || (f & kPatFailed)) {
+      need[i] = 1;
+    } else if (f & kPatOverflow) {
+      status[i] = HPM_E_OVERFLOW;
+      errors[i] = "embedding count exceeds 2^64-1";
+    } else {
+      counts[i] = B->host_counts[i];
+    }
+  }
+}
+
+int batch_persistent(hpm_graph* G, int32_t n, const hpm_pattern* patterns, const int32_t* modes,
+                     hipStream_t stream, const hpm_match_opts* opts, const hpm_batch_config* cfgp,
+                     uint64_t* counts, int32_t* status) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (n < 0 || (n > 0 && (!patterns || !modes || !counts || !status)))
+    fail(HPM_E_ARG, "NULL batch arrays");
+  if (n > 65535) fail(HPM_E_ARG, "at most 65535 patterns per batch");
+  const hpm_batch_config cfg = batch_defaults(cfgp);
+  uint32_t flags = 0;
+  uint64_t budget = 0, limit = 0;
+  read_opts(opts, &flags, &budget, &limit);
+  flags &= ~(uint32_t)HPM_F_TIMING;
+  hip_check(hipSetDevice(G->device), "hipSetDevice");
+  hpm_batch_stats bst{};
+  bst.struct_size = sizeof(hpm_batch_stats);
+  std::vector<std::string> errors((size_t)n);
+  std::vector<char> need((size_t)n, 0);
+  if (budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    uint64_t pooled = 0;
+    {
+      std::lock_guard<std::mutex> lk(G->mu);
+      for (const BatchSpace* b : G->bpool) pooled += b->held();
+    }
+    budget = ((uint64_t)free_b + pooled) / 4;
+  }
+  if (limit || (flags & HPM_F_OVERLAP)) {
+    // first-k and the overlap test are options of the single-query path
+    for (int32_t i = 0; i < n; ++i) need[i] = 1;
+  } else if (n > 0) {
+    run_persistent(G, n, patterns, modes, stream, flags, budget, cfg, counts, status, errors,
+                   need, bst);
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    if (!need[i]) continue;
+    bst.fallback_patterns++;
+    try {
+      status[i] = match_one(G, &patterns[i], modes[i], stream, flags, budget, &counts[i], nullptr,
+                            0, nullptr, nullptr, limit);
+    } catch (const Failure& f) {
+      status[i] = f.status;
+      errors[i] = f.msg;
+    }
+  }
+  bst.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  t_bstats = bst;
+  for (int32_t i = 0; i < n; ++i)
+    if (status[i] != HPM_OK) {
+      t_error = "pattern " + std::to_string(i) + ": " + errors[i];
+      return status[i];
+    }
+  return HPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1664,6 +1982,69 @@ int hpm_batch_tune(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
     if (best_ms) *best_ms = best;
     return HPM_OK;
   });
+}
+
+int hpm_match_batch_persistent(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
+                               const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                               const hpm_batch_config* cfg, uint64_t* counts, int32_t* status) {
+  return guarded([&]() -> int {
+    if (!kPersistentEnabled)
+      fail(HPM_E_UNSUPPORTED, "the persistent batched launch is switched off (it stalled on "
+                              "the device and no cause has been shown)");
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    return batch_persistent(const_cast<hpm_graph*>(gc), n, patterns, modes,
+                            static_cast<hipStream_t>(stream), opts, cfg, counts, status);
+  });
+}
+
+int hpm_batch_autotune(const hpm_graph* gc, int32_t n, const hpm_pattern* patterns,
+                       const int32_t* modes, void* stream, const hpm_match_opts* opts,
+                       hpm_batch_config* best, double* best_ms) {
+  return guarded([&]() -> int {
+    if (!kPersistentEnabled)
+      fail(HPM_E_UNSUPPORTED, "the persistent batched launch is switched off (it stalled on "
+                              "the device and no cause has been shown)");
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (!best) fail(HPM_E_ARG, "best is NULL");
+    if (n <= 0) fail(HPM_E_ARG, "empty batch");
+    hpm_graph* G = const_cast<hpm_graph*>(gc);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<uint64_t> counts((size_t)n), first((size_t)n);
+    std::vector<int32_t> status((size_t)n);
+    hpm_batch_config c = batch_defaults(nullptr);
+    // one untimed run sizes the scratch and gives the reference counts
+    int st = batch_persistent(G, n, patterns, modes, s, opts, &c, first.data(), status.data());
+    if (st != HPM_OK) return st;
+    double top = -1.0;
+    hpm_batch_config arg = c;
+    for (int32_t items : {1, 2, 4})
+      for (int32_t rows : {64, 256, 1024})
+        for (int64_t work : {int64_t(4096), int64_t(65536)})
+          for (int32_t strat : {HPM_X_MAPPED, HPM_X_SHORTER}) {
+            c.items_per_lane = items;
+            c.chunk_rows = rows;
+            c.task_work = work;
+            c.strategy = strat;
+            st = batch_persistent(G, n, patterns, modes, s, opts, &c, counts.data(),
+                                  status.data());
+            if (st != HPM_OK) return st;
+            if (counts != first) fail(HPM_E_INTERNAL, "batch counts differ between settings");
+            const double ms = t_bstats.fallback_patterns ? t_bstats.ms_total : t_bstats.kernel_ms;
+            if (top < 0.0 || ms < top) {
+              top = ms;
+              arg = c;
+            }
+          }
+    *best = arg;
+    if (best_ms) *best_ms = top;
+    return HPM_OK;
+  });
+}
+
+int hpm_last_batch_stats(hpm_batch_stats* out) {
+  if (!out) return HPM_E_ARG;
+  *out = t_bstats;
+  return HPM_OK;
 }
 
 int hpm_server_create(hpm_server** out, const hpm_graph* gc, const hpm_server_opts* opts) {

@@ -20,7 +20,7 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
-ABI_VERSION = 3  # HPM_ABI_VERSION of include/hpm.h
+ABI_VERSION = 4  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
@@ -38,7 +38,8 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match", "hpm_match_batch",
-           "hpm_batch_tune",
+           "hpm_batch_tune", "hpm_match_batch_persistent", "hpm_batch_autotune",
+           "hpm_last_batch_stats",
            "hpm_server_create", "hpm_server_submit", "hpm_server_poll", "hpm_server_read_stats",
            "hpm_server_destroy", "hpm_plan_order", "hpm_last_stats", "hpm_status_string",
            "hpm_last_error", "hpm_abi_version")
@@ -73,6 +74,26 @@ class _Stats(ctypes.Structure):
                 ("overlap_removed", ctypes.c_uint64), ("counted_rows", ctypes.c_uint64),
                 ("counted_work", ctypes.c_uint64), ("filter_rows", ctypes.c_uint64),
                 ("filter_entries", ctypes.c_uint64), ("filter_pieces", ctypes.c_uint64)]
+
+
+X_MAPPED, X_SHORTER = 0, 1
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("items_per_lane", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int32), ("strategy", ctypes.c_int32),
+                ("task_work", ctypes.c_int64), ("blocks_per_cu", ctypes.c_int32),
+                ("idle_us", ctypes.c_int32)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("error_bits", ctypes.c_uint32),
+                ("tasks", ctypes.c_uint64 * 4), ("launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("queue_slots", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
+                ("fixed_bytes", ctypes.c_uint64), ("arena_capacity", ctypes.c_uint64),
+                ("grid", ctypes.c_int32), ("fallback_patterns", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -125,6 +146,13 @@ def load() -> ctypes.CDLL:
                                     I32, P, P]
     lib.hpm_batch_tune.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
                                    ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+    lib.hpm_match_batch_persistent.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P,
+                                               ctypes.POINTER(_Opts),
+                                               ctypes.POINTER(_BatchConfig), P, P]
+    lib.hpm_batch_autotune.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P,
+                                       ctypes.POINTER(_Opts), ctypes.POINTER(_BatchConfig),
+                                       ctypes.POINTER(ctypes.c_double)]
+    lib.hpm_last_batch_stats.argtypes = [ctypes.POINTER(_BatchStats)]
     lib.hpm_server_create.argtypes = [ctypes.POINTER(P), P, ctypes.POINTER(_ServerOpts)]
     lib.hpm_server_submit.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P, U64,
                                       ctypes.POINTER(U64)]
@@ -138,7 +166,9 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-                 "hpm_match_batch", "hpm_batch_tune", "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
+                 "hpm_match_batch", "hpm_batch_tune", "hpm_match_batch_persistent",
+                 "hpm_batch_autotune", "hpm_last_batch_stats",
+                 "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
                  "hpm_server_read_stats", "hpm_server_destroy", "hpm_plan_order",
                  "hpm_last_stats"):
         getattr(lib, name).restype = ctypes.c_int
@@ -330,6 +360,81 @@ def batch_tune(g: Graph, patterns, modes, stream=None, budget: int | None = None
     _check(lib.hpm_batch_tune(g.handle, n, structs, _ptr(md), _stream_handle(stream),
                               ctypes.byref(opts), ctypes.byref(w), ctypes.byref(ms)))
     return int(w.value), float(ms.value)
+
+
+def _batch_structs(g, patterns):
+    for p in patterns:
+        _check_columns(g, p)
+    structs = (_Pattern * max(len(patterns), 1))()
+    keep = []
+    for i, p in enumerate(patterns):
+        st, arrs = _pattern_struct(p)
+        structs[i] = st
+        keep.append(arrs)
+    return structs, keep
+
+
+def _config(cfg):
+    if cfg is None:
+        return None
+    c = _BatchConfig(ctypes.sizeof(_BatchConfig), int(cfg.get("items_per_lane", 0)),
+                     int(cfg.get("chunk_rows", 0)), int(cfg.get("strategy", X_MAPPED)),
+                     int(cfg.get("task_work", 0)), int(cfg.get("blocks_per_cu", 0)),
+                     int(cfg.get("idle_us", 0)))
+    return ctypes.byref(c), c
+
+
+def match_batch_persistent(g: Graph, patterns, modes, config=None, stream=None,
+                           budget: int | None = None, flags: int = 0, max_matches: int = 0):
+    """Counts of many patterns in one persistent launch (hpm_match_batch_persistent).
+
+    config: None or a dict with any of items_per_lane, chunk_rows, strategy,
+    task_work, blocks_per_cu, idle_us.  Returns (counts, statuses); raises HpmError if
+    any pattern failed.
+    """
+    lib = load()
+    n = len(patterns)
+    structs, keep = _batch_structs(g, patterns)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    counts = np.zeros(max(n, 1), dtype=np.uint64)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), int(max_matches))
+    cfg = _config(config)
+    _check(lib.hpm_match_batch_persistent(g.handle, n, structs, _ptr(md), _stream_handle(stream),
+                                          ctypes.byref(opts), cfg[0] if cfg else None,
+                                          _ptr(counts), _ptr(status)))
+    return [int(c) for c in counts[:n]], [int(x) for x in status[:n]]
+
+
+def batch_autotune(g: Graph, patterns, modes, stream=None, budget: int | None = None,
+                   flags: int = 0):
+    """Fastest persistent-launch configuration for this batch (hpm_batch_autotune):
+    returns (config dict, milliseconds)."""
+    lib = load()
+    n = len(patterns)
+    structs, keep = _batch_structs(g, patterns)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), 0)
+    best = _BatchConfig(ctypes.sizeof(_BatchConfig), 0, 0, 0, 0, 0, 0)
+    ms = ctypes.c_double()
+    _check(lib.hpm_batch_autotune(g.handle, n, structs, _ptr(md), _stream_handle(stream),
+                                  ctypes.byref(opts), ctypes.byref(best), ctypes.byref(ms)))
+    return ({"items_per_lane": best.items_per_lane, "chunk_rows": best.chunk_rows,
+             "strategy": best.strategy, "task_work": best.task_work,
+             "blocks_per_cu": best.blocks_per_cu}, float(ms.value))
+
+
+def last_batch_stats() -> dict:
+    """Statistics of this thread's last match_batch_persistent call."""
+    lib = load()
+    st = _BatchStats()
+    _check(lib.hpm_last_batch_stats(ctypes.byref(st)))
+    return {"error_bits": st.error_bits, "launches": st.launches, "tasks_scan": st.tasks[2],
+            "tasks_expand": st.tasks[3], "queue_slots": st.queue_slots,
+            "arena_bytes": st.arena_bytes, "scratch_bytes": st.scratch_bytes,
+            "fixed_bytes": st.fixed_bytes, "arena_capacity": st.arena_capacity, "grid": st.grid,
+            "fallback_patterns": st.fallback_patterns, "kernel_ms": st.kernel_ms,
+            "ms_total": st.ms_total}
 
 
 class Server:

@@ -37,7 +37,8 @@ def test_struct_mirrors_match_the_header(tmp_path):
     # the header's structs
     mirrors = {"hpm_match_opts": hb._Opts, "hpm_server_opts": hb._ServerOpts,
                "hpm_query_result": hb._QueryResult, "hpm_server_stats": hb._ServerStats,
-               "hpm_match_stats": hb._Stats, "hpm_pattern": hb._Pattern}
+               "hpm_match_stats": hb._Stats, "hpm_pattern": hb._Pattern,
+               "hpm_batch_config": hb._BatchConfig, "hpm_batch_stats": hb._BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hpm.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -204,3 +205,14 @@ def test_motif_orders_are_valid():
         p = make_pattern(k, arcs, 1, 1)
         assert is_weakly_connected(k, arcs)
         _check_order(p, hpm.plan_order(p, 1, 1))
+
+
+def test_persistent_batch_entry_points_are_switched_off():
+    # the persistent batched launch stalled on the device; its entry points
+    # refuse to run before touching any argument or the device
+    lib = hpm.load()
+    assert lib.hpm_match_batch_persistent(None, 0, None, None, None, None, None, None,
+                                          None) == hpm.hpm.E_UNSUPPORTED
+    assert lib.hpm_batch_autotune(None, 0, None, None, None, None, None, None) == \
+        hpm.hpm.E_UNSUPPORTED
+    assert "switched off" in lib.hpm_last_error().decode()
