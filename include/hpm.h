@@ -39,7 +39,8 @@ extern "C" {
 
 /* 3: hpm_match_stats.filter_pieces appended; HPM_F_TIMING_KINDS. */
 /* 4: hpm_match_batch_persistent, hpm_batch_autotune, hpm_last_batch_stats. */
-#define HPM_ABI_VERSION 4
+/* 5: hpm_match_noalloc. */
+#define HPM_ABI_VERSION 5
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -187,6 +188,26 @@ typedef struct {
  */
 int hpm_match(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* stream,
               const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap);
+
+/*
+ * hpm_match_noalloc -- hpm_match for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as hpm_match; the
+ * call itself calls no hipMalloc, hipFree or other allocating routine.  Its
+ * scratch is a fixed 128 MiB device array that the library holds on every GPU
+ * it runs on until the process ends (resolved once per device, on that
+ * device's first call).  A call may use a quarter of it as its budget
+ * (opts->hbm_budget_bytes is capped there; frontiers are expanded in chunks
+ * that fit, so results never depend on it); a pattern whose minimum chunk
+ * does not fit fails with HPM_E_NOMEM.  Calls on one GPU share that GPU's
+ * array: the library runs them one at a time (a later call waits for an
+ * earlier one to return), and each call clears what it needs.  Calls from
+ * other code that write the same array would race with it.  HPM_F_TIMING is
+ * ignored (timing events are created on demand).
+ */
+int hpm_match_noalloc(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* stream,
+                      const hpm_match_opts* opts, uint64_t* count, int32_t* mappings,
+                      uint64_t cap);
 
 /*
  * hpm_match_batch -- count the embeddings of n patterns in one resident graph.

@@ -79,22 +79,53 @@ int guarded(F&& f) {
   }
 }
 
-// Owned device allocation that can grow.
+// Bump allocation from a fixed device region (the allocation-free entry
+// point): regions are handed out in 256-byte units and never returned; a
+// call resets it before it starts.
+struct Carve {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  void* take(size_t want) {
+    const size_t n = (want + 255) / 256 * 256;
+    if (n > size - used)
+      fail(HPM_E_NOMEM, "the call needs more than the " + std::to_string(size >> 20) +
+                            " MiB of allocation-free scratch");
+    void* p = base + used;
+    used += n;
+    return p;
+  }
+};
+// Set for the duration of an allocation-free call on this thread.
+thread_local Carve* t_carve = nullptr;
+
+// Owned device allocation that can grow.  While t_carve is set, growth takes
+// a new region from it (at least twice the old size) instead of hipMalloc.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool carved = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !carved) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    carved = false;
   }
   // Make room for at least `want` bytes; contents are not preserved.
   void ensure(size_t want, hipStream_t stream) {
     if (want <= bytes) return;
+    if (t_carve) {
+      // the old region stays valid for work already queued on it
+      const size_t n = std::max(want, 2 * bytes);
+      if (p && !carved) fail(HPM_E_INTERNAL, "allocation-free call on an allocated buffer");
+      p = t_carve->take(n);
+      bytes = n;
+      carved = true;
+      return;
+    }
     if (p) {
       hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
       release();
@@ -1871,9 +1902,90 @@ int batch_persistent(hpm_graph* G, int32_t n, const hpm_pattern* patterns, const
   return HPM_OK;
 }
 
+// ------------------------------------------------------------ allocation-free match
+
+// The device scratch of hpm_match_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` is only a handle; its device address
+// comes from hipGetSymbolAddress, once per device (noalloc_state).
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+
+struct NoAllocState {
+  std::mutex mu;              // one allocation-free call per device at a time
+  bool ready = false;
+  char* dev = nullptr;        // device address of this device's scratch
+  Workspace* ws = nullptr;    // host-side bookkeeping, never freed
+  unsigned long long host[kCntNum];  // readback slots (pageable)
+  DevPlan host_plan;
+};
+NoAllocState g_noalloc[kMaxDevices];
+
+// Resolve the device's scratch address once (the device must be current).
+NoAllocState& noalloc_state(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(HPM_E_UNSUPPORTED, "device index out of range");
+  NoAllocState& S = g_noalloc[device];
+  if (!S.ready) {
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (!ptr) fail(HPM_E_DEVICE, "no device address for the allocation-free scratch");
+    S.dev = static_cast<char*>(ptr);
+    S.ws = new Workspace();
+    S.ws->host = S.host;
+    S.ws->host_plan = &S.host_plan;
+    S.ready = true;
+  }
+  return S;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hpm_match_noalloc(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
+                      const hpm_match_opts* opts, uint64_t* count, int32_t* mappings,
+                      uint64_t cap) {
+  return guarded([&]() -> int {
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (!count) fail(HPM_E_ARG, "count is NULL");
+    uint32_t flags = 0;
+    uint64_t budget = 0, limit = 0;
+    read_opts(opts, &flags, &budget, &limit);
+    // events are created on demand: no per-kernel timing here
+    flags &= ~(uint32_t)(HPM_F_TIMING | (0xffu << 16));
+    hpm_graph* G = const_cast<hpm_graph*>(gc);
+    int cur = 0;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != G->device) hip_check(hipSetDevice(G->device), "hipSetDevice");
+    struct Restore {
+      int prev, now;
+      ~Restore() {
+        if (prev != now) (void)hipSetDevice(prev);
+      }
+    } restore{cur, G->device};
+    NoAllocState& S = [&]() -> NoAllocState& {
+      static std::mutex init_mu;
+      std::lock_guard<std::mutex> lk(init_mu);
+      return noalloc_state(G->device);
+    }();
+    std::lock_guard<std::mutex> lk(S.mu);
+    // Buffers grow by at least doubling, so what a call carves stays within
+    // four times what it asks for: it runs with a quarter of the scratch as
+    // its budget (or less, if the caller asks for less).
+    const uint64_t most = kNoAllocBytes / 4;
+    if (budget == 0 || budget > most) budget = most;
+    Carve carve{S.dev, kNoAllocBytes, 0};
+    Workspace* W = S.ws;
+    W->release_all();  // forget the previous call's regions (nothing is freed)
+    t_carve = &carve;
+    struct Clear {
+      ~Clear() { t_carve = nullptr; }
+    } clear;
+    return match_one(G, p, (int)mode, static_cast<hipStream_t>(stream), flags, budget, count,
+                     mappings, cap, &t_stats, W, limit);
+  });
+}
 
 int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
               const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap) {

@@ -20,7 +20,7 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
-ABI_VERSION = 4  # HPM_ABI_VERSION of include/hpm.h
+ABI_VERSION = 5  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
@@ -37,7 +37,8 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
            "reduce", "filter")
 
 # Every function include/hpm.h declares.
-EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match", "hpm_match_batch",
+EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
+           "hpm_match_noalloc", "hpm_match_batch",
            "hpm_batch_tune", "hpm_match_batch_persistent", "hpm_batch_autotune",
            "hpm_last_batch_stats",
            "hpm_server_create", "hpm_server_submit", "hpm_server_poll", "hpm_server_read_stats",
@@ -142,6 +143,8 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(U64)]
     lib.hpm_match.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
                               ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
+    lib.hpm_match_noalloc.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
+                                      ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
     lib.hpm_match_batch.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
                                     I32, P, P]
     lib.hpm_batch_tune.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
@@ -166,6 +169,7 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
+                 "hpm_match_noalloc",
                  "hpm_match_batch", "hpm_batch_tune", "hpm_match_batch_persistent",
                  "hpm_batch_autotune", "hpm_last_batch_stats",
                  "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
@@ -312,6 +316,27 @@ def match(g: Graph, p, mode: int, mappings: bool = False, cap: int | None = None
                        ctypes.byref(cnt), ctypes.c_void_p(buf.data_ptr()), int(cap))
     _check(st)
     return int(cnt.value), buf[: int(cnt.value)]
+
+
+def match_noalloc(g: Graph, p, mode: int, out=None, stream=None, budget: int | None = None,
+                  flags: int = 0, max_matches: int = 0):
+    """hpm_match_noalloc: as match(), for callers that cannot allocate device
+    memory.  out: None (count only) or a caller-owned int32 device tensor
+    [cap, k] that receives the rows.  Returns (count, out[:count] or None);
+    the count may exceed cap (then HpmError with E_TRUNCATED is raised)."""
+    lib = load()
+    _check_columns(g, p)
+    s, keep = _pattern_struct(p)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, int(budget or 0), int(max_matches))
+    cnt = ctypes.c_uint64()
+    ptr, cap = None, 0
+    if out is not None:
+        if out.dim() != 2 or out.shape[1] != p.k or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [cap, k] int32 device tensor")
+        ptr, cap = ctypes.c_void_p(out.data_ptr()), int(out.shape[0])
+    _check(lib.hpm_match_noalloc(g.handle, ctypes.byref(s), int(mode), _stream_handle(stream),
+                                 ctypes.byref(opts), ctypes.byref(cnt), ptr, cap))
+    return int(cnt.value), (out[: int(cnt.value)] if out is not None else None)
 
 
 def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
