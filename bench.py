@@ -303,6 +303,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: apply the neighbour-overlap test to depth-2 rows (HPM_F_OVERLAP)")
+    ap.add_argument("--lookahead", type=int, default=0,
+                    help="1: apply the frontier look-ahead to the rows of every depth "
+                         "(HPM_F_LOOKAHEAD)")
     ap.add_argument("--batched-ref", type=int, default=1,
                     help="also run the step's queries as one batched call (outside the "
                          "timed region; 0 for hardware-counter runs)")
@@ -338,7 +341,8 @@ def main():
     log(f"graph resident: {dg.info()['device_bytes'] / 2**20:.1f} MiB")
     stream = torch.cuda.current_stream()
 
-    extra_flags = hpm.F_OVERLAP if args.overlap else 0
+    extra_flags = (hpm.F_OVERLAP if args.overlap else 0) | \
+        (hpm.F_LOOKAHEAD if args.lookahead else 0)
     flush_buf = (torch.empty(args.flush_mib << 18, dtype=torch.int32, device="cuda")
                  if args.flush_mib else None)
 
@@ -555,7 +559,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n": g.n, "m": g.m,
-                   "overlap_test": bool(args.overlap),
+                   "overlap_test": bool(args.overlap), "lookahead": bool(args.lookahead),
                    "queries": ([f"{p.name}/{'iso' if mode == 0 else 'mono'}" for p, mode in runs]
                                if len(runs) <= 16 else f"{len(runs)} patterns"),
                    "matches_per_step": matches_per_step},
@@ -569,6 +573,7 @@ def main():
                        "work": st["work"][2:p.k], "raw_work": st["raw_work"][2:p.k],
                        "filtered_lists": st["filtered_lists"],
                        "overlap_removed": st["overlap_removed"],
+                       "lookahead_removed": st["lookahead_removed"],
                        "kernel_ms": {k: round(v, 4) for k, v in st["kernel_ms"].items() if v}}
                       for st, (p, mode) in zip(per_query_stats, runs)],
         "roofline": roofline,

@@ -40,7 +40,8 @@ extern "C" {
 /* 3: hpm_match_stats.filter_pieces appended; HPM_F_TIMING_KINDS. */
 /* 4: hpm_match_batch_persistent, hpm_batch_autotune, hpm_last_batch_stats. */
 /* 5: hpm_match_noalloc. */
-#define HPM_ABI_VERSION 5
+/* 6: HPM_F_LOOKAHEAD, hpm_match_stats.lookahead_removed. */
+#define HPM_ABI_VERSION 6
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -143,6 +144,13 @@ typedef struct {
                                  neighbours (either direction) than pattern     \
                                  positions 0 and 1 do.  Sound, same result;     \
                                  one more pass over the depth-2 rows. */
+#define HPM_F_LOOKAHEAD 0x10u /* frontier look-ahead (VF2's frontier sets,     \
+                                 Sec. II-C; Alg. 3 builds them for the         \
+                                 injected state): before a depth is extended, \
+                                 drop rows in which a later pattern position   \
+                                 adjacent to a mapped one has no candidate     \
+                                 consistent with all its mapped neighbours.    \
+                                 Sound, same result; one pass per depth. */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(hpm_match_opts); 16 = the layout without
@@ -469,6 +477,7 @@ typedef struct {
   uint64_t filter_entries;       /* list entries the pre-filter read (all its groups)  */
   uint64_t filter_pieces;        /* blocks its list pass ran: one per group, more for  */
                                  /* lists longer than one piece of 1024 entries         */
+  uint64_t lookahead_removed;    /* rows dropped by HPM_F_LOOKAHEAD (all depths)       */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

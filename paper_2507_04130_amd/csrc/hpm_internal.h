@@ -196,6 +196,15 @@ hipError_t launch_rows2_gather(const int32_t* sparse, const int64_t* prefix, int
 // number (zero it first).
 hipError_t launch_overlap_filter(const DevGraph& g, const int32_t* rows, int64_t n, int32_t need,
                                  int32_t* out, unsigned long long* cursor, hipStream_t stream);
+// Frontier look-ahead on n rows of d mapped positions: a row is kept (copied
+// to out, unspecified order, *cursor += kept; zero it first) when every
+// position in fmask that is adjacent to a mapped position has at least one
+// candidate consistent with all its mapped neighbours.  vbits: the call's
+// validator bitmaps (position p at vbits + p * words).
+hipError_t launch_lookahead_filter(const DevGraph& g, const DevPlan* plan, const uint32_t* vbits,
+                                   int64_t words, const int32_t* rows, int64_t n, int32_t d,
+                                   uint32_t fmask, int32_t* out, unsigned long long* cursor,
+                                   hipStream_t stream);
 // Blocks for an arc scan over `arcs` arcs with out_mode 0 or 1 (one per tile).
 int64_t edge_scan_blocks(int64_t arcs);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]

@@ -409,9 +409,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows2(const int2* __restrict_
 // are distinct common neighbours of their images, so a depth-2 row (u, v)
 // whose u and v share fewer neighbours (either direction, u and v excluded)
 // than positions 0 and 1 share in the pattern (need) extends to nothing.  One
-// lane per row walks the neighbours of the endpoint with the smaller degree
-// and stops as soon as `need` common neighbours are found; the rows that pass
-// are written to out (one atomic per wavefront).
+// wavefront per row walks the out- and then in-list of the endpoint with the
+// smaller degree, 64 entries per step, and probes each entry in both lists of
+// the other endpoint; an in-neighbour that is also an out-neighbour is counted
+// once.  The walk stops as soon as `need` common neighbours are found, or as
+// soon as the entries left cannot reach `need`.  Rows that pass go to out
+// (unspecified order, one atomic per row kept).
 __device__ __forceinline__ bool adjacent_either(const DevGraph& g, int32_t y, int32_t w) {
   return find_in(g.out_nbrs, g.out_off[y], g.out_off[y + 1], w) >= 0 ||
          find_in(g.in_nbrs, g.in_off[y], g.in_off[y + 1], w) >= 0;
@@ -423,40 +426,129 @@ __global__ __launch_bounds__(kBlock) void k_overlap_filter(DevGraph g, const int
                                                            unsigned long long* __restrict__ cursor) {
   const int lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  for (int64_t base = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 64; base < n;
-       base += nwaves * 64) {
-    const int64_t i = base + lane;
-    bool keep = false;
-    int2 rw = make_int2(0, 0);
-    if (i < n) {
-      rw = rows[i];
-      int32_t x = rw.x, y = rw.y;
-      const int32_t dx = (g.out_off[x + 1] - g.out_off[x]) + (g.in_off[x + 1] - g.in_off[x]);
-      const int32_t dy = (g.out_off[y + 1] - g.out_off[y]) + (g.in_off[y + 1] - g.in_off[y]);
-      if (dy < dx) {
-        const int32_t t = x;
-        x = y;
-        y = t;
-      }
-      int32_t cnt = 0;
-      for (int32_t j = g.out_off[x]; j < g.out_off[x + 1] && cnt < need; ++j) {
-        const int32_t w = g.out_nbrs[j];
-        if (w != y && adjacent_either(g, y, w)) ++cnt;
-      }
-      for (int32_t j = g.in_off[x]; j < g.in_off[x + 1] && cnt < need; ++j) {
-        const int32_t w = g.in_nbrs[j];
-        // a reciprocal neighbour was already counted from the out-list
-        if (w != y && find_in(g.out_nbrs, g.out_off[x], g.out_off[x + 1], w) < 0 &&
-            adjacent_either(g, y, w))
-          ++cnt;
-      }
-      keep = cnt >= need;
+  for (int64_t i = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); i < n; i += nwaves) {
+    const int2 rw = rows[i];
+    int32_t x = rw.x, y = rw.y;
+    const int32_t dx = (g.out_off[x + 1] - g.out_off[x]) + (g.in_off[x + 1] - g.in_off[x]);
+    const int32_t dy = (g.out_off[y + 1] - g.out_off[y]) + (g.in_off[y + 1] - g.in_off[y]);
+    if (dy < dx) {
+      const int32_t t = x;
+      x = y;
+      y = t;
     }
-    const uint64_t m = __ballot(keep);
+    const int32_t olo = g.out_off[x], ohi = g.out_off[x + 1];
+    const int32_t ilo = g.in_off[x], ihi = g.in_off[x + 1];
+    const int32_t nout = ohi - olo, total = nout + (ihi - ilo);
+    int32_t cnt = 0;
+    for (int32_t base = 0; base < total; base += 64) {
+      const int32_t j = base + lane;
+      bool hit = false;
+      if (j < total) {
+        const bool from_out = j < nout;
+        const int32_t w = from_out ? g.out_nbrs[olo + j] : g.in_nbrs[ilo + j - nout];
+        hit = w != y && adjacent_either(g, y, w);
+        // a reciprocal neighbour was already counted from the out-list
+        if (hit && !from_out) hit = find_in(g.out_nbrs, olo, ohi, w) < 0;
+      }
+      cnt += __popcll(__ballot(hit));
+      const int32_t left = total - (base + 64);
+      if (cnt >= need || cnt + (left > 0 ? left : 0) < need) break;  // wave-uniform
+    }
+    if (lane == 0 && cnt >= need) out[atomicAdd(cursor, 1ull)] = rw;
+  }
+}
+
+// ------------------------------------------------------------ frontier look-ahead
+//
+// VF2's look-ahead on the frontier sets (Sec. II-C; the T sets Alg. 3 builds
+// for the injected state): a pattern position b beyond the next one that is
+// adjacent to a mapped position lies in the pattern's frontier, and in any
+// embedding its image is an unmapped target vertex that passes b's vertex
+// validator and is joined to the image of every mapped position related to b
+// by a target arc in the same direction with that arc's predicate (and, for
+// induced isomorphism, to no other mapped image).  A row for which some such
+// b has no candidate at all extends to nothing.  A group of G lanes takes one
+// row (64 / G rows per wavefront): for each frontier position b (mask
+// fmask), the shortest list among the mapped positions related to b is
+// walked G entries per step until one entry satisfies every condition; a row
+// with a position that has none is dropped.  Rows kept go to out
+// (unspecified order).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_lookahead_filter(
+    DevGraph g, const DevPlan* __restrict__ P, const uint32_t* __restrict__ vbits, int64_t words,
+    const int32_t* __restrict__ rows, int64_t n, int32_t d, uint32_t fmask,
+    int32_t* __restrict__ out, unsigned long long* __restrict__ cursor) {
+  constexpr int kRowsPerWave = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / G, gl = lane % G;
+  const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (grp * G);
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const bool iso = P->mode == 0;
+  const int32_t k = P->k;
+  const uint32_t mapped = (1u << d) - 1u;
+  for (int64_t base = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * kRowsPerWave;
+       base < n; base += nwaves * kRowsPerWave) {
+    const int64_t i = base + grp;
+    const int32_t* row = rows + (i < n ? i : 0) * d;
+    bool keep = i < n;
+    for (int b = 0; b < k; ++b) {  // wave-uniform loop
+      if (!((fmask >> b) & 1u)) continue;
+      const uint32_t fw = P->fwd[b] & mapped, bw = P->bwd[b] & mapped;
+      if ((fw | bw) == 0) continue;
+      // pivot: the shortest list of a related mapped position
+      int32_t best = 0, pq = 0, plo = 0;
+      bool pout = false;
+      if (keep) {
+        best = INT32_MAX;
+        for (int q = 0; q < d; ++q) {
+          const int32_t fq = row[q];
+          if ((fw >> q) & 1u) {
+            const int32_t L = g.out_off[fq + 1] - g.out_off[fq];
+            if (L < best) { best = L; pq = q; pout = true; plo = g.out_off[fq]; }
+          }
+          if ((bw >> q) & 1u) {
+            const int32_t L = g.in_off[fq + 1] - g.in_off[fq];
+            if (L < best) { best = L; pq = q; pout = false; plo = g.in_off[fq]; }
+          }
+        }
+      }
+      const uint32_t* bbits = vbits + (int64_t)b * words;
+      bool found = !keep;  // dropped rows take no further steps
+      for (int32_t at = 0;; at += G) {
+        const bool walking = !found && at < best;
+        if (!__any(walking)) break;  // wave-uniform
+        bool ok = walking && at + gl < best;
+        if (ok) {
+          const int32_t pos = plo + at + gl;
+          const int32_t c = pout ? g.out_nbrs[pos] : g.in_nbrs[pos];
+          ok = test_bit(bbits, c);
+          if (ok) ok = pout ? arc_ok(g, P, pq, b, pos) : arc_ok_in(g, P, b, pq, pos);
+          for (int q = 0; q < d && ok; ++q) ok = row[q] != c;
+          for (int q = 0; q < d && ok; ++q) {
+            const int32_t fq = row[q];
+            const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
+            if ((arc_in && !(q == pq && pout)) || (!arc_in && iso)) {
+              const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
+              ok = arc_in ? (e >= 0 && arc_ok(g, P, q, b, e)) : e < 0;
+            }
+            if (ok && ((arc_out && !(q == pq && !pout)) || (!arc_out && iso))) {
+              const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
+              ok = arc_out ? (e >= 0 && arc_ok_in(g, P, b, q, e)) : e < 0;
+            }
+          }
+        }
+        found = found || (__ballot(ok) & gmask) != 0;
+      }
+      keep = keep && found && best > 0;
+    }
+    const uint64_t kept = __ballot(keep && gl == 0);
     unsigned long long slot0 = 0;
-    if (lane == 0 && m) slot0 = atomicAdd(cursor, (unsigned long long)__popcll(m));
+    if (lane == 0 && kept) slot0 = atomicAdd(cursor, (unsigned long long)__popcll(kept));
     slot0 = __shfl(slot0, 0);
-    if (keep) out[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = rw;
+    if (keep) {
+      const unsigned long long slot = slot0 + __popcll(kept & ((1ull << (grp * G)) - 1ull));
+      for (int x = gl; x < d; x += G) out[slot * d + x] = row[x];
+    }
   }
 }
 
@@ -1844,6 +1936,18 @@ hipError_t launch_overlap_filter(const DevGraph& g, const int32_t* rows, int64_t
   const int grid = grid_for((n + 63) / 64, kWaves, kMaxGridSimple);
   k_overlap_filter<<<grid, kBlock, 0, stream>>>(g, reinterpret_cast<const int2*>(rows), n, need,
                                                 reinterpret_cast<int2*>(out), cursor);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookahead_filter(const DevGraph& g, const DevPlan* plan, const uint32_t* vbits,
+                                   int64_t words, const int32_t* rows, int64_t n, int32_t d,
+                                   uint32_t fmask, int32_t* out, unsigned long long* cursor,
+                                   hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  constexpr int kGroup = 64;  // lanes per row (16 was measured 1.5x slower on the connectome)
+  const int grid = grid_for((n * kGroup + 63) / 64, kWaves, kMaxGridSimple);
+  k_lookahead_filter<kGroup><<<grid, kBlock, 0, stream>>>(g, plan, vbits, words, rows, n, d,
+                                                          fmask, out, cursor);
   return hipGetLastError();
 }
 

@@ -155,6 +155,8 @@ struct Workspace {
   DevBuf crest, cbsum;
   // per depth: prefix sums of short-row lengths and of long-row tile counts
   DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
+  // frontier look-ahead: the rows of each depth that pass it
+  DevBuf la[kMaxK];
   unsigned long long* host = nullptr;  // pinned readback slots
   DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
   std::vector<hipEvent_t> events;
@@ -171,7 +173,8 @@ struct Workspace {
                fpslot.bytes + fpdesc.bytes + ftmp.bytes + crest.bytes + cbsum.bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
-           off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes;
+           off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes +
+           la[d].bytes;
     return s;
   }
   void release_all() {
@@ -187,6 +190,7 @@ struct Workspace {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
       fpool[d].release(); off2[d].release();
       soff[d].release(); toff[d].release(); sbsum[d].release(); tbsum[d].release();
+      la[d].release();
     }
   }
 };
@@ -536,6 +540,7 @@ struct Matcher {
   bool stopped = false;
   uint32_t done[kMaxK] = {};  // per depth: relations the pre-filtered lists enforce
   int32_t overlap_need = 0;   // common neighbours of positions 0 and 1 (overlap test on)
+  bool lookahead = false;     // frontier look-ahead on the rows of every depth
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -864,9 +869,36 @@ struct Matcher {
     return *T > 0;
   }
 
+  // Frontier look-ahead mask for rows of d mapped positions: the positions
+  // after the next one (d) that are adjacent to a mapped position.
+  uint32_t frontier_mask(int32_t d) const {
+    const uint32_t mapped = (1u << d) - 1u;
+    uint32_t m = 0;
+    for (int32_t b = d + 1; b < k; ++b)
+      if ((host_plan.fwd[b] | host_plan.bwd[b]) & mapped) m |= 1u << b;
+    return m;
+  }
+
   // Extend the r rows (each d entries) in `rows` to full embeddings.
   void process_depth(int32_t d, const int32_t* rows, int64_t r) {
     if (r == 0) return;
+    const uint32_t fmask = lookahead ? frontier_mask(d) : 0u;
+    if (fmask) {
+      // rows with a frontier position that has no candidate extend to nothing
+      need(W->la[d], (size_t)r * d * sizeof(int32_t));
+      zero_counter(kCntCursor);
+      launch(HPM_K_FILTER, [&] {
+        return hpm::launch_lookahead_filter(g, dplan(), W->vbits.as<uint32_t>(), bit_words(), rows,
+                                            r, d, fmask, W->la[d].as<int32_t>(),
+                                            counters() + kCntCursor, stream);
+      });
+      const int64_t kept = (int64_t)read_counter(kCntCursor);
+      if (kept > r) fail(HPM_E_INTERNAL, "look-ahead filter overflow");
+      st.lookahead_removed += (uint64_t)(r - kept);
+      rows = W->la[d].as<int32_t>();
+      r = kept;
+      if (r == 0) return;
+    }
     st.rows[d] += r;
     int64_t* off = W->off[d].as<int64_t>();
     int2* piv = W->piv[d].as<int2>();
@@ -1381,6 +1413,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     M.chunk = chunk;
     M.budget = budget;
     M.limit = limit;
+    M.lookahead = (flags & HPM_F_LOOKAHEAD) != 0;
     if ((flags & HPM_F_OVERLAP) && k >= 3) {
       // pattern vertices adjacent (either direction) to both of the first two
       const int32_t u = order[0], v = order[1];
@@ -1873,7 +1906,7 @@ int batch_persistent(hpm_graph* G, int32_t n, const hpm_pattern* patterns, const
     }
     budget = ((uint64_t)free_b + pooled) / 4;
   }
-  if (limit || (flags & HPM_F_OVERLAP)) {
+  if (limit || (flags & (HPM_F_OVERLAP | HPM_F_LOOKAHEAD))) {
     // first-k and the overlap test are options of the single-query path
     for (int32_t i = 0; i < n; ++i) need[i] = 1;
   } else if (n > 0) {

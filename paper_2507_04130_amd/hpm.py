@@ -20,10 +20,11 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
-ABI_VERSION = 5  # HPM_ABI_VERSION of include/hpm.h
+ABI_VERSION = 6  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
+F_LOOKAHEAD = 0x10
 
 
 def F_TIMING_KINDS(*names):
@@ -74,7 +75,8 @@ class _Stats(ctypes.Structure):
                 ("filtered_lists", ctypes.c_uint64), ("raw_work", ctypes.c_uint64 * (MAX_K + 1)),
                 ("overlap_removed", ctypes.c_uint64), ("counted_rows", ctypes.c_uint64),
                 ("counted_work", ctypes.c_uint64), ("filter_rows", ctypes.c_uint64),
-                ("filter_entries", ctypes.c_uint64), ("filter_pieces", ctypes.c_uint64)]
+                ("filter_entries", ctypes.c_uint64), ("filter_pieces", ctypes.c_uint64),
+                ("lookahead_removed", ctypes.c_uint64)]
 
 
 X_MAPPED, X_SHORTER = 0, 1
@@ -540,7 +542,7 @@ def last_stats() -> dict:
         "overlap_removed": s.overlap_removed,
         "counted_rows": s.counted_rows, "counted_work": s.counted_work,
         "filter_rows": s.filter_rows, "filter_entries": s.filter_entries,
-        "filter_pieces": s.filter_pieces,
+        "filter_pieces": s.filter_pieces, "lookahead_removed": s.lookahead_removed,
     }
 
 

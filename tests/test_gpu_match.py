@@ -475,3 +475,39 @@ def test_overlap_test_changes_nothing():
             assert c1 == oracle.match(g, p, mode, threads=8, rows=False).count
     say(f"overlap test removed {removed} depth-2 rows")
     assert removed > 0
+
+
+def test_lookahead_changes_nothing():
+    # HPM_F_LOOKAHEAD drops rows with a frontier position that has no
+    # candidate; counts and rows must equal the oracle's (both modes, labels
+    # and predicates, alone and with the overlap test, and with a budget that
+    # forces several chunks), and rows must be dropped somewhere
+    g = rmat(10, 1 << 13, seed=51)
+    dg = hpm.Graph.from_host(g)
+    removed = 0
+    cases = [(motif(n), m) for n in ("clique4_minus1", "ffl_tail", "cycle4", "star3_back")
+             for m in (ISO, MONO)]
+    rng = np.random.default_rng(808)
+    for i in range(12):
+        cases.append((random_pattern(rng, kmin=4, kmax=7), ISO if i % 2 else MONO))
+    for p, mode in cases:
+        want = oracle.match(g, p, mode, threads=8)
+        for flags, budget in ((hpm.F_LOOKAHEAD, None), (hpm.F_LOOKAHEAD | hpm.F_OVERLAP, None),
+                              (hpm.F_LOOKAHEAD, 600_000)):
+            c1, _ = hpm.match(dg, p, mode, flags=flags, budget=budget)
+            removed += hpm.last_stats()["lookahead_removed"]
+            assert c1 == want.count, (p.name, mode, flags)
+        if want.count <= 1_000_000:
+            _, r1 = gpu_rows(dg, p, mode, flags=hpm.F_LOOKAHEAD)
+            np.testing.assert_array_equal(r1, want.rows)
+    say(f"look-ahead removed {removed} rows")
+    assert removed > 0
+    dg.close()
+    # five-vertex motifs on a connectome-shaped graph (weights, reciprocity)
+    gc = configs.c3_graph(n=20_000, m=150_000)
+    dc = hpm.Graph.from_host(gc)
+    for p in configs.c3_patterns():
+        want = oracle.match(gc, p, MONO, threads=8, rows=False)
+        c1, _ = hpm.match(dc, p, MONO, flags=hpm.F_LOOKAHEAD)
+        assert c1 == want.count, p.name
+    dc.close()
