@@ -234,7 +234,7 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
     import numpy as np
     from synth import configs
     arrivals, idx = configs.c5_trace(qps, n, len(runs))
-    warm = n // 10
+    warm = min(100, n // 10)
     lat = np.zeros(n)
     got = [None] * n
     if kind == "served":
@@ -248,6 +248,8 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
             late[i] = time.perf_counter() - t0 - arrivals[i]
             p, mode = runs[idx[i]]
             tickets.append(srv.submit(p, mode))
+            if i % 500 == 499:
+                log(f"  {kind} {qps} q/s: {i + 1} of {n} submitted")
         for i, t in enumerate(tickets):
             r = srv.poll(t, wait=True)
             assert r["status"] == 0, r
@@ -267,6 +269,8 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
             p, mode = runs[idx[i]]
             got[i], _ = hpm.match(dg, p, mode, stream=stream)
             done[i] = time.perf_counter() - t0
+            if i % 500 == 499:
+                log(f"  {kind} {qps} q/s: {i + 1} of {n} done")
         lat = done - arrivals
     bad = [i for i in range(n) if got[i] != expected[idx[i]]]
     assert not bad, f"{kind} counts differ from the oracle's at {bad[:8]}"
@@ -295,10 +299,11 @@ def main():
                     choices=["rmat20", "er1k", "chunglu", "batch256", "serve"])
     ap.add_argument("--batch-workers", type=int, default=0,
                     help="host threads / streams of the batched call (batch256); 0 = tuned")
-    ap.add_argument("--qps", default="100,500,1000,2000",
+    ap.add_argument("--qps", default="10,20,50,100,200,500",
                     help="arrival rates of the serve workload (comma separated)")
-    ap.add_argument("--serve-queries", type=int, default=400,
-                    help="queries per arrival rate (serve); the first tenth are warm-up")
+    ap.add_argument("--serve-queries", type=int, default=2000,
+                    help="queries per arrival rate (serve); the first 100 (at most a tenth) "
+                         "are warm-up")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--overlap", type=int, default=0,

@@ -41,7 +41,9 @@ extern "C" {
 /* 4: hpm_match_batch_persistent, hpm_batch_autotune, hpm_last_batch_stats. */
 /* 5: hpm_match_noalloc. */
 /* 6: HPM_F_LOOKAHEAD, hpm_match_stats.lookahead_removed. */
-#define HPM_ABI_VERSION 6
+/* 7: hpm_scan_survivors, HPM_F_COUNT_FROM_MAX. */
+/* 8: HPM_F_NO_ARC_INDEX, hpm_match_stats.index_arcs. */
+#define HPM_ABI_VERSION 8
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -144,6 +146,14 @@ typedef struct {
                                  neighbours (either direction) than pattern     \
                                  positions 0 and 1 do.  Sound, same result;     \
                                  one more pass over the depth-2 rows. */
+#define HPM_F_COUNT_FROM_MAX 0x20u /* test only: the running count starts at  \
+                                 2^64 - 1, so a count-only call that finds an   \
+                                 embedding fails with HPM_E_OVERFLOW (exercises \
+                                 the wrap check of the count reduction). */
+#define HPM_F_NO_ARC_INDEX 0x40u /* do not restrict the adjacency the       \
+                                 extension reads to the arcs that can match     \
+                                 (monomorphism: the loosest predicate over all  \
+                                 pattern arcs).  Same result. */
 #define HPM_F_LOOKAHEAD 0x10u /* frontier look-ahead (VF2's frontier sets,     \
                                  Sec. II-C; Alg. 3 builds them for the         \
                                  injected state): before a depth is extended, \
@@ -196,6 +206,25 @@ typedef struct {
  */
 int hpm_match(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* stream,
               const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap);
+
+/*
+ * hpm_scan_survivors -- the injected states alone (Sec. III-C, Alg. 4): the
+ * vertex validator for pattern positions 0 and 1 (Alg. 2), then every target
+ * arc as a candidate image of the pattern arc between them with the edge
+ * validator's checks (Alg. 3: both vertex flags, the arc's predicate, the
+ * reverse arc required with its predicate for a reciprocal pattern pair and,
+ * under induced isomorphism, forbidden otherwise).  Positions are those of
+ * hpm_plan_order (flags as for hpm_match).  *count receives the number of
+ * surviving arcs; rows (NULL, or a DEVICE int32 buffer of cap rows of 2)
+ * receives them as (image of position 0, image of position 1), in an order
+ * that is the same on every call but otherwise unspecified (tiles of arcs in
+ * arc order, rows within a tile interleaved).  Nothing is extended.  Errors:
+ * as hpm_match; HPM_E_TRUNCATED when *count > cap (the first cap rows are
+ * written).
+ */
+int hpm_scan_survivors(const hpm_graph* g, const hpm_pattern* p, hpm_mode mode, void* stream,
+                       const hpm_match_opts* opts, uint64_t* count, int32_t* rows,
+                       uint64_t cap);
 
 /*
  * hpm_match_noalloc -- hpm_match for callers that cannot allocate device
@@ -363,7 +392,10 @@ int hpm_last_batch_stats(hpm_batch_stats* out);
  * stays within the budget.  Admission is in arrival order, except that a query
  * that does not fit may be overtaken by later ones that do, at most 32 times.
  * Queries submitted while others run join them on the device (continuous
- * batching); this is the served form of the edge-centric search on a large
+ * batching).  While some workers are idle, one of them polls for arrivals
+ * instead of sleeping (one host core), so a query submitted to an idle server
+ * starts without a thread wake-up.  This is the served form of the
+ * edge-centric search on a large
  * resident graph (Sec. I and Sec. IV-D: whole-brain connectomes held in
  * memory and queried repeatedly).
  */
@@ -478,6 +510,7 @@ typedef struct {
   uint64_t filter_pieces;        /* blocks its list pass ran: one per group, more for  */
                                  /* lists longer than one piece of 1024 entries         */
   uint64_t lookahead_removed;    /* rows dropped by HPM_F_LOOKAHEAD (all depths)       */
+  uint64_t index_arcs;           /* arcs of the arc-predicate index (0: not built)     */
 } hpm_match_stats;
 
 int hpm_last_stats(hpm_match_stats* out);

@@ -19,7 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hpm_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HPM_ORACLE_LIB: load another build of the same source (the sanitizer test's)
+_LIB = os.environ.get("HPM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -254,7 +254,7 @@ void sort_rows_impl(int32_t* rows, uint64_t count, int32_t k) {
   std::vector<int32_t> tmp((size_t)count * k);
   for (uint64_t i = 0; i < count; ++i)
     std::memcpy(&tmp[i * k], rows + idx[i] * k, sizeof(int32_t) * k);
-  std::memcpy(rows, tmp.data(), sizeof(int32_t) * tmp.size());
+  if (!tmp.empty()) std::memcpy(rows, tmp.data(), sizeof(int32_t) * tmp.size());
 }
 
 }  // namespace
@@ -329,7 +329,7 @@ int og_match(int32_t n, int64_t m, const int64_t* out_off, const int32_t* out_nb
     int32_t* rows = (int32_t*)std::malloc(sizeof(int32_t) * (size_t)total * k + 1);
     size_t off = 0;
     for (Search* s : per) {
-      if (!s) continue;
+      if (!s || s->rows.empty()) continue;  // memcpy from an empty vector's NULL is undefined
       std::memcpy(rows + off, s->rows.data(), sizeof(int32_t) * s->rows.size());
       off += s->rows.size();
     }

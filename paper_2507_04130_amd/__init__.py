@@ -8,5 +8,5 @@ from .hpm import (ANY, EQ, GE, ISO, MONO, F_NO_FILTER, F_NO_REORDER, F_OVERLAP, 
                   HpmError, Server,
                   X_MAPPED, X_SHORTER, abi_version, batch_autotune, batch_tune,
                   last_batch_stats, last_stats, load, match, match_batch, match_batch_persistent,
-                  match_noalloc,
+                  match_noalloc, scan_survivors, F_COUNT_FROM_MAX, F_NO_ARC_INDEX,
                   plan_order, status_string)

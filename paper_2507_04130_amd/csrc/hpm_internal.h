@@ -205,6 +205,19 @@ hipError_t launch_lookahead_filter(const DevGraph& g, const DevPlan* plan, const
                                    int64_t words, const int32_t* rows, int64_t n, int32_t d,
                                    uint32_t fmask, int32_t* out, unsigned long long* cursor,
                                    hipStream_t stream);
+// Arc-predicate index (adjacency restricted to the arcs whose columns in
+// cmask lie in [lo[c], hi[c]]).  flags: pos[0..m] = exclusive prefix counts of
+// the passing arcs (pos[m] = their number); bsum needs ceil((m + 1) / 4096)
+// + 2 entries.  fill: off_out[0..n] = pos[off[v]], the passing arcs' targets
+// into nbrs_out and their first ncols columns into cols_out (rows stay sorted).
+hipError_t launch_arc_index_flags(const int32_t* const* cols, const int32_t* lo,
+                                  const int32_t* hi, uint32_t cmask, int64_t m, int32_t* pos,
+                                  int64_t* bsum, hipStream_t stream);
+hipError_t launch_arc_index_fill(const int32_t* off, int32_t n, const int32_t* nbrs,
+                                 const int32_t* const* cols, int32_t ncols, const int32_t* lo,
+                                 const int32_t* hi, uint32_t cmask, int64_t m, const int32_t* pos,
+                                 int32_t* off_out, int32_t* nbrs_out, int32_t* const* cols_out,
+                                 hipStream_t stream);
 // Blocks for an arc scan over `arcs` arcs with out_mode 0 or 1 (one per tile).
 int64_t edge_scan_blocks(int64_t arcs);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]

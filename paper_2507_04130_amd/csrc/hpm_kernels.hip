@@ -1830,6 +1830,104 @@ __global__ __launch_bounds__(kBlock) void k_reduce_counts(const unsigned long lo
   }
 }
 
+// ------------------------------------------------------------ arc-predicate index
+//
+// Adjacency restricted to the arcs that pass one attribute predicate (every
+// column c in cmask within [lo[c], hi[c]]): pos[e] = 1 for a passing arc e
+// (0 otherwise, pos[m] = 0), an exclusive scan turns pos into the new index
+// of every arc, then the passing arcs and their columns are compacted and the
+// row offsets become off'[v] = pos[off[v]].  Rows stay sorted.
+struct ArcPred {
+  int32_t lo[kMaxCols], hi[kMaxCols];
+  uint32_t cmask;
+};
+
+__device__ __forceinline__ bool arc_pred_ok(const int32_t* const* cols, const ArcPred& P,
+                                            int64_t e) {
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < kMaxCols; ++c)
+    if ((P.cmask >> c) & 1u) {
+      const int32_t x = cols[c][e];
+      ok = ok && x >= P.lo[c] && x <= P.hi[c];
+    }
+  return ok;
+}
+
+struct ColPtrs {
+  const int32_t* c[kMaxCols];
+};
+struct ColOut {
+  int32_t* c[kMaxCols];
+};
+
+__global__ __launch_bounds__(kBlock) void k_arc_flags(ColPtrs cols, ArcPred P, int64_t m,
+                                                      int32_t* __restrict__ pos) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e <= m;
+       e += (int64_t)gridDim.x * kBlock)
+    pos[e] = (e < m && arc_pred_ok(cols.c, P, e)) ? 1 : 0;
+}
+
+constexpr int kI32ScanItems = 16;
+constexpr int kI32ScanTile = kBlock * kI32ScanItems;
+
+// Per-block sums of int32 values a[0..len), blocks of kI32ScanTile entries.
+__global__ __launch_bounds__(kBlock) void k_i32_block_sums(const int32_t* __restrict__ a,
+                                                           int64_t len,
+                                                           int64_t* __restrict__ bsum) {
+  __shared__ int64_t s_scan[kWaves + 1];
+  const int64_t base = (int64_t)blockIdx.x * kI32ScanTile + (int64_t)threadIdx.x * kI32ScanItems;
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kI32ScanItems; ++i)
+    if (base + i < len) s += a[base + i];
+  const int64_t tot = block_sum<int64_t>(s, s_scan);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// a[0..len) -> exclusive prefix sums, block offsets from the scanned bsum.
+__global__ __launch_bounds__(kBlock) void k_i32_scan_apply(int32_t* __restrict__ a, int64_t len,
+                                                           const int64_t* __restrict__ bsum) {
+  __shared__ int64_t s_scan[kWaves + 1];
+  const int64_t base = (int64_t)blockIdx.x * kI32ScanTile + (int64_t)threadIdx.x * kI32ScanItems;
+  int32_t v[kI32ScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kI32ScanItems; ++i) {
+    v[i] = base + i < len ? a[base + i] : 0;
+    s += v[i];
+  }
+  int64_t tot;
+  int64_t run = block_exclusive_scan<int64_t>(s, s_scan, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kI32ScanItems; ++i) {
+    if (base + i < len) a[base + i] = (int32_t)run;
+    run += v[i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_arc_compact(const int32_t* __restrict__ nbrs,
+                                                        ColPtrs cols, ArcPred P, int32_t ncols,
+                                                        int64_t m, const int32_t* __restrict__ pos,
+                                                        int32_t* __restrict__ nbrs_out,
+                                                        ColOut cols_out) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * kBlock) {
+    if (pos[e + 1] == pos[e]) continue;  // the arc fails the predicate
+    const int32_t at = pos[e];
+    nbrs_out[at] = nbrs[e];
+    for (int c = 0; c < ncols; ++c) cols_out.c[c][at] = cols.c[c][e];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_arc_offsets(const int32_t* __restrict__ off, int32_t n,
+                                                        const int32_t* __restrict__ pos,
+                                                        int32_t* __restrict__ off_out) {
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v <= n;
+       v += (int64_t)gridDim.x * kBlock)
+    off_out[v] = pos[off[v]];
+}
+
 inline int grid_for(int64_t items, int64_t per_block, int max_grid) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -1969,6 +2067,56 @@ hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
   if (r <= 0) return hipSuccess;
   const int nb = (int)(((int64_t)r + kPivotTile - 1) / kPivotTile);
   k_row_pivot<<<nb, kBlock, 0, stream>>>(g, plan, d, rows, r, piv, off, bsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_arc_index_flags(const int32_t* const* cols, const int32_t* lo,
+                                  const int32_t* hi, uint32_t cmask, int64_t m, int32_t* pos,
+                                  int64_t* bsum, hipStream_t stream) {
+  ColPtrs cp{};
+  ArcPred P{};
+  for (int c = 0; c < kMaxCols; ++c) {
+    cp.c[c] = cols[c];
+    P.lo[c] = lo[c];
+    P.hi[c] = hi[c];
+  }
+  P.cmask = cmask;
+  k_arc_flags<<<grid_for(m + 1, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(cp, P, m, pos);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // exclusive scan of pos[0..m]: block sums, one-block scan of those, apply
+  const int64_t len = m + 1;
+  const int nb = (int)((len + kI32ScanTile - 1) / kI32ScanTile);
+  k_i32_block_sums<<<nb, kBlock, 0, stream>>>(pos, len, bsum);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_scan_bsum<<<1, kBlock, 0, stream>>>(bsum, nb, bsum + nb + 1, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_i32_scan_apply<<<nb, kBlock, 0, stream>>>(pos, len, bsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_arc_index_fill(const int32_t* off, int32_t n, const int32_t* nbrs,
+                                 const int32_t* const* cols, int32_t ncols, const int32_t* lo,
+                                 const int32_t* hi, uint32_t cmask, int64_t m, const int32_t* pos,
+                                 int32_t* off_out, int32_t* nbrs_out, int32_t* const* cols_out,
+                                 hipStream_t stream) {
+  ColPtrs cp{};
+  ColOut co{};
+  ArcPred P{};
+  for (int c = 0; c < kMaxCols; ++c) {
+    cp.c[c] = cols[c];
+    co.c[c] = cols_out[c];
+    P.lo[c] = lo[c];
+    P.hi[c] = hi[c];
+  }
+  P.cmask = cmask;
+  if (m > 0)
+    k_arc_compact<<<grid_for(m, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+        nbrs, cp, P, ncols, m, pos, nbrs_out, co);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_arc_offsets<<<grid_for((int64_t)n + 1, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+      off, n, pos, off_out);
   return hipGetLastError();
 }
 

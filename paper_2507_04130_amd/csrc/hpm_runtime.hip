@@ -157,6 +157,10 @@ struct Workspace {
   DevBuf soff[kMaxK], toff[kMaxK], sbsum[kMaxK], tbsum[kMaxK];
   // frontier look-ahead: the rows of each depth that pass it
   DevBuf la[kMaxK];
+  // arc-predicate index: arc positions, block sums, and the restricted
+  // out- and in-adjacency with their attribute columns
+  DevBuf apos, absum, aoff_out, anbrs_out, aoff_in, anbrs_in;
+  DevBuf acol_out[kMaxCols], acol_in[kMaxCols];
   unsigned long long* host = nullptr;  // pinned readback slots
   DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
   std::vector<hipEvent_t> events;
@@ -170,7 +174,10 @@ struct Workspace {
                blkcount.bytes + blkprefix.bytes + rows2.bytes + rows2d.bytes +
                fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
                fslot_region.bytes + fcount.bytes + fpbase.bytes + fpbsum.bytes + fpcnt.bytes +
-               fpslot.bytes + fpdesc.bytes + ftmp.bytes + crest.bytes + cbsum.bytes;
+               fpslot.bytes + fpdesc.bytes + ftmp.bytes + crest.bytes + cbsum.bytes +
+               apos.bytes + absum.bytes + aoff_out.bytes + anbrs_out.bytes + aoff_in.bytes +
+               anbrs_in.bytes;
+    for (int c = 0; c < kMaxCols; ++c) s += acol_out[c].bytes + acol_in[c].bytes;
     for (int d = 0; d < kMaxK; ++d)
       s += off[d].bytes + piv[d].bytes + bsum[d].bytes + rows[d].bytes + fpool[d].bytes +
            off2[d].bytes + soff[d].bytes + toff[d].bytes + sbsum[d].bytes + tbsum[d].bytes +
@@ -186,6 +193,12 @@ struct Workspace {
     fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); fpdesc.release();
     ftmp.release();
     crest.release(); cbsum.release();
+    apos.release(); absum.release(); aoff_out.release(); anbrs_out.release();
+    aoff_in.release(); anbrs_in.release();
+    for (int c = 0; c < kMaxCols; ++c) {
+      acol_out[c].release();
+      acol_in[c].release();
+    }
     for (int d = 0; d < kMaxK; ++d) {
       off[d].release(); piv[d].release(); bsum[d].release(); rows[d].release();
       fpool[d].release(); off2[d].release();
@@ -520,11 +533,14 @@ constexpr int64_t kCountMinPerRow = 64;
 // Pre-filter pivot lists only when a depth has at least this many candidates.
 constexpr int64_t kFilterMinWork = int64_t(1) << 22;
 
+double sample_fraction(const std::vector<int32_t>& smp, int32_t lo, int32_t hi);
+
 struct Matcher {
   hpm_graph* G;
   Workspace* W;
   hipStream_t stream;
-  DevGraph g;
+  DevGraph g;   // the adjacency the validator and the extension read
+  DevGraph gs;  // the whole graph, read by the arc scan
   DevPlan host_plan;
   int32_t k;
   int32_t* maps;
@@ -541,6 +557,12 @@ struct Matcher {
   uint32_t done[kMaxK] = {};  // per depth: relations the pre-filtered lists enforce
   int32_t overlap_need = 0;   // common neighbours of positions 0 and 1 (overlap test on)
   bool lookahead = false;     // frontier look-ahead on the rows of every depth
+  bool indexed = false;       // g reads the arc-predicate index
+  // survivors only: the depth-2 rows after the validators are copied to
+  // surv_out ([surv_cap][2], positions 0 and 1) and nothing is extended
+  int32_t* surv_out = nullptr;
+  uint64_t surv_cap = 0;
+  bool survivors_only = false;
   hpm_match_stats st{};
   struct Pending {
     int kind;
@@ -747,7 +769,11 @@ struct Matcher {
     int t_use = -1;
     for (int t = 2; t >= 1 && t_use < 0; --t)
       if (masks[t] && 2 * distinct[t] <= r && groups(t)) t_use = t;
-    if (t_use < 0 && groups(0)) t_use = 0;
+    // Grouping by pivot list alone filters a list by the validator and the
+    // pivot arc's predicate; over the arc-predicate index the predicate holds
+    // already and the pass costs more than it removes (connectome: 10% of the
+    // candidates for 19 ms per step), so it is left out there.
+    if (t_use < 0 && !indexed && groups(0)) t_use = 0;
     const uint32_t use_mask = t_use > 0 ? masks[t_use] : 0u;
     if (nslots == 0) return;
     // Long lists are split over several blocks (pieces of kFilterPiece
@@ -1041,6 +1067,118 @@ struct Matcher {
     if (limit && !stopped && read_total() >= limit) stopped = true;
   }
 
+  // Arc-predicate index (monomorphism only): every pattern arc's predicate
+  // implies the loosest range per column over all pattern arcs, so an arc that
+  // fails it is never the image of a pattern arc.  After the arc scan (which
+  // reads the whole graph) the validator and the extension then read
+  // adjacency restricted to the arcs that pass it: shorter candidate lists and
+  // membership searches, the same embeddings (non-arcs, which induced
+  // isomorphism checks, need the whole graph, so it is not used there).
+  // Built when the column samples say at most three quarters of the arcs
+  // pass and the buffers fit the budget.
+  void build_arc_index(uint32_t flags) {
+    if (host_plan.mode != HPM_MONO || k < 3 || (flags & HPM_F_NO_ARC_INDEX)) return;
+    const int32_t nc = G->n_ecols;
+    if (nc == 0) return;
+    int32_t lo[kMaxCols], hi[kMaxCols];
+    for (int c = 0; c < kMaxCols; ++c) {
+      lo[c] = INT32_MAX;
+      hi[c] = INT32_MIN;
+    }
+    uint32_t cmask = (1u << nc) - 1u;
+    for (int32_t a = 0; a < k; ++a)
+      for (int32_t b = 0; b < k; ++b) {
+        const bool arc = (a < b) ? ((host_plan.fwd[b] >> a) & 1u) : (a > b && ((host_plan.bwd[a] >> b) & 1u));
+        if (!arc) continue;
+        for (int32_t c = 0; c < nc; ++c) {
+          if (!((host_plan.amask[a][b] >> c) & 1u)) {
+            cmask &= ~(1u << c);
+            continue;
+          }
+          lo[c] = std::min(lo[c], host_plan.alo[a][b][c]);
+          hi[c] = std::max(hi[c], host_plan.ahi[a][b][c]);
+        }
+      }
+    if (cmask == 0) return;
+    double frac = 1.0;
+    for (int32_t c = 0; c < nc; ++c)
+      if ((cmask >> c) & 1u) frac = std::min(frac, sample_fraction(G->esample[c], lo[c], hi[c]));
+    if (frac > 0.75) return;
+    const int64_t m = G->m;
+    const int64_t nb = (m + 1 + 4095) / 4096;
+    const uint64_t fixed = (uint64_t)(m + 1) * 4 + (uint64_t)(nb + 2) * 8 +
+                           2 * (uint64_t)(G->n + 1) * 4;
+    if (planned + extra(W->apos, (size_t)(m + 1) * 4) > budget ||
+        planned + fixed > budget)
+      return;
+    need(W->apos, (size_t)(m + 1) * 4);
+    need(W->absum, (size_t)(nb + 2) * 8);
+    int32_t* pos = W->apos.as<int32_t>();
+    const int32_t* cols_out[kMaxCols] = {};
+    const int32_t* cols_in[kMaxCols] = {};
+    for (int c = 0; c < kMaxCols; ++c) {
+      cols_out[c] = G->ecols[c].as<int32_t>();
+      cols_in[c] = G->ecols_in[c].as<int32_t>();
+    }
+    // out side: positions, the number of passing arcs, then the arrays
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_arc_index_flags(cols_out, lo, hi, cmask, m, pos,
+                                         W->absum.as<int64_t>(), stream);
+    });
+    const int64_t mp = (int64_t)read_i32(pos + m);
+    const uint64_t arrays = 2 * ((uint64_t)(G->n + 1) * 4 + (uint64_t)mp * 4 * (1 + nc));
+    if (mp < 0 || mp > m) fail(HPM_E_INTERNAL, "arc index count out of range");
+    if (planned + arrays > budget) return;
+    need(W->aoff_out, (size_t)(G->n + 1) * 4);
+    need(W->anbrs_out, (size_t)std::max<int64_t>(mp, 1) * 4);
+    need(W->aoff_in, (size_t)(G->n + 1) * 4);
+    need(W->anbrs_in, (size_t)std::max<int64_t>(mp, 1) * 4);
+    int32_t* co[kMaxCols] = {};
+    int32_t* ci[kMaxCols] = {};
+    for (int32_t c = 0; c < nc; ++c) {
+      need(W->acol_out[c], (size_t)std::max<int64_t>(mp, 1) * 4);
+      need(W->acol_in[c], (size_t)std::max<int64_t>(mp, 1) * 4);
+      co[c] = W->acol_out[c].as<int32_t>();
+      ci[c] = W->acol_in[c].as<int32_t>();
+    }
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_arc_index_fill(G->out_off.as<int32_t>(), G->n,
+                                        G->out_nbrs.as<int32_t>(), cols_out, nc, lo, hi, cmask, m,
+                                        pos, W->aoff_out.as<int32_t>(),
+                                        W->anbrs_out.as<int32_t>(), co, stream);
+    });
+    // in side (the transpose: the same arcs pass)
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_arc_index_flags(cols_in, lo, hi, cmask, m, pos,
+                                         W->absum.as<int64_t>(), stream);
+    });
+    launch(HPM_K_FILTER, [&] {
+      return hpm::launch_arc_index_fill(G->in_off.as<int32_t>(), G->n, G->in_nbrs.as<int32_t>(),
+                                        cols_in, nc, lo, hi, cmask, m, pos,
+                                        W->aoff_in.as<int32_t>(), W->anbrs_in.as<int32_t>(), ci,
+                                        stream);
+    });
+    g.m = (int32_t)mp;
+    g.out_off = W->aoff_out.as<int32_t>();
+    g.out_nbrs = W->anbrs_out.as<int32_t>();
+    g.in_off = W->aoff_in.as<int32_t>();
+    g.in_nbrs = W->anbrs_in.as<int32_t>();
+    for (int32_t c = 0; c < nc; ++c) {
+      g.ecol[c] = W->acol_out[c].as<int32_t>();
+      g.ecol_in[c] = W->acol_in[c].as<int32_t>();
+    }
+    st.index_arcs = (uint64_t)mp;
+    indexed = true;
+  }
+
+  int32_t read_i32(const int32_t* p) {
+    hip_check(hipMemcpyAsync(W->host + kCntSlots, p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             stream),
+              "readback");
+    sync();
+    return *reinterpret_cast<const int32_t*>(W->host + kCntSlots);
+  }
+
   void run() {
     const int64_t m = G->m;
     st.arcs_scanned = (uint64_t)m;
@@ -1048,13 +1186,13 @@ struct Matcher {
       return hpm::launch_vertex_validator(g, dplan(), W->vbits.as<uint32_t>(), bit_words(),
                                           stream);
     });
-    if (k == 2) {
+    if (k == 2 && !survivors_only) {
       const int grid = grid_for(m, hpm::kScanTile);
       uint64_t c;
       if (maps) {
         zero_counter(kCntCursor);
         launch(HPM_K_EDGE_SCAN, [&] {
-          return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 2, maps,
+          return hpm::launch_edge_scan(gs, dplan(), bits0(), bits1(), 0, (int32_t)m, 2, maps,
                                        counters() + kCntCursor, emit_cap(),
                                        W->partials.as<unsigned long long>(), grid, stream);
         });
@@ -1063,7 +1201,7 @@ struct Matcher {
         const int nb = (int)hpm::edge_scan_blocks(m);
         need(W->blkcount, (size_t)nb * sizeof(unsigned long long));
         launch(HPM_K_EDGE_SCAN, [&] {
-          return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), 0, (int32_t)m, 1, nullptr,
+          return hpm::launch_edge_scan(gs, dplan(), bits0(), bits1(), 0, (int32_t)m, 1, nullptr,
                                        nullptr, 0, W->blkcount.as<unsigned long long>(), nb,
                                        stream);
         });
@@ -1088,7 +1226,7 @@ struct Matcher {
       need(W->blkprefix, (size_t)(grid / hpm::kPivotTile + 2) * sizeof(int64_t));
       int64_t* cnt = W->blkcount.as<int64_t>();
       launch(HPM_K_EDGE_SCAN, [&] {
-        return hpm::launch_edge_scan(g, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1, 0,
+        return hpm::launch_edge_scan(gs, dplan(), bits0(), bits1(), (int32_t)e0, (int32_t)e1, 0,
                                      W->rows2.as<int32_t>(), nullptr,
                                      (unsigned long long)(e1 - e0),
                                      reinterpret_cast<unsigned long long*>(cnt), grid, stream);
@@ -1106,6 +1244,16 @@ struct Matcher {
         return hpm::launch_rows2_gather(W->rows2.as<int32_t>(), cnt, grid, (int32_t)e0,
                                         (int32_t)e1, W->rows2d.as<int32_t>(), s2, stream);
       });
+      if (survivors_only) {
+        const uint64_t done = st.survivors - (uint64_t)s2;  // rows of earlier chunks
+        if (surv_out && done < surv_cap) {
+          const uint64_t n = std::min<uint64_t>((uint64_t)s2, surv_cap - done);
+          hip_check(hipMemcpyAsync(surv_out + done * 2, W->rows2d.p, n * 2 * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, stream),
+                    "survivor copy");
+        }
+        continue;
+      }
       if (overlap_need > 0) {
         // the sparse scan regions are free again: the rows that pass go there
         zero_counter(kCntCursor);
@@ -1123,9 +1271,19 @@ struct Matcher {
       }
       check_limit();
     }
+    if (survivors_only) {
+      st.count = st.survivors;
+      return;
+    }
     st.count = read_total();
     if (limit) st.count = std::min(st.count, limit);
   }
+};
+
+// Output of a survivors-only call (hpm_scan_survivors).
+struct SurvivorsOut {
+  int32_t* rows;
+  uint64_t cap;
 };
 
 constexpr uint64_t kMinChunkRows = hpm::kExpandTile;
@@ -1313,7 +1471,8 @@ inline uint64_t row_bytes(int32_t d) { return 4 * (uint64_t)d + 17; }
 // Workspace: NULL takes one from the graph's pool (returned on exit).
 int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, uint32_t flags,
               uint64_t budget, uint64_t* count, int32_t* mappings, uint64_t cap,
-              hpm_match_stats* stats, Workspace* own = nullptr, uint64_t limit = 0) {
+              hpm_match_stats* stats, Workspace* own = nullptr, uint64_t limit = 0,
+              const SurvivorsOut* surv = nullptr) {
     const auto t0 = std::chrono::steady_clock::now();
     if (mode != HPM_ISO && mode != HPM_MONO) fail(HPM_E_ARG, "mode must be HPM_ISO or HPM_MONO");
     PatternInfo info = check_pattern(p, G->n_vcols, G->n_ecols);
@@ -1368,7 +1527,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     if (budget < fixed) fail(HPM_E_NOMEM, "scratch budget below the fixed part");
     uint64_t avail = budget - fixed;
     int64_t cap2 = 0, chunk = 0;
-    if (k >= 3) {
+    if (k >= 3 || surv) {
       uint64_t per_row_deep = 0;
       for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += row_bytes(d);
       const uint64_t m_round =
@@ -1406,7 +1565,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     if (!W->host_plan)
       hip_check(hipHostMalloc((void**)&W->host_plan, sizeof(DevPlan)), "hipHostMalloc");
 
-    Matcher M{G, W, stream, G->view(), plan, k, mappings, mappings ? cap : 0,
+    Matcher M{G, W, stream, G->view(), G->view(), plan, k, mappings, mappings ? cap : 0,
               (flags & HPM_F_TIMING) != 0, (flags & HPM_F_NO_FILTER) == 0, max_grid};
     M.timed_kinds = (flags >> 16) & 0xffu ? (flags >> 16) & 0xffu : 0xffu;
     M.cap2 = cap2;
@@ -1426,7 +1585,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
     M.need(W->vbits, (size_t)std::max<int64_t>(M.bit_words(), 1) * k * sizeof(uint32_t));
     M.need(W->counters, kCntNum * sizeof(unsigned long long));
     M.need(W->partials, (size_t)max_grid * 2 * sizeof(unsigned long long));
-    if (k >= 3) {
+    if (k >= 3 || surv) {
       const int64_t rows2 = std::min<int64_t>(cap2, std::max<int64_t>(G->m, 1));
       M.need(W->rows2, (size_t)rows2 * 2 * sizeof(int32_t));
     }
@@ -1437,6 +1596,21 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
               "plan upload");
     hip_check(hipMemsetAsync(W->counters.p, 0, kCntNum * sizeof(unsigned long long), stream),
               "memset");
+    if (flags & HPM_F_COUNT_FROM_MAX) {
+      // test only: the running total starts at 2^64 - 1, so the first
+      // embedding counted wraps it
+      static const unsigned long long kMax = ~0ull;
+      hip_check(hipMemcpyAsync(M.counters() + kCntTotal, &kMax, sizeof(kMax),
+                               hipMemcpyHostToDevice, stream),
+                "counter seed");
+    }
+    if (surv) {
+      M.survivors_only = true;
+      M.surv_out = surv->rows;
+      M.surv_cap = surv->cap;
+    } else {
+      M.build_arc_index(flags);
+    }
     M.run();
     M.sync();
     M.st.struct_size = sizeof(hpm_match_stats);
@@ -1553,6 +1727,13 @@ struct hpm_server {
   bool stop = false;
   std::string start_error;
   std::vector<std::thread> threads;
+  // Dispatch without a wake-up: while the server has idle workers, one of them
+  // (the spinner) polls `events` instead of sleeping on cv_work, so a query
+  // that arrives at an idle server starts within microseconds; the others
+  // sleep.  A worker that takes a query wakes one sleeper to take over.
+  std::atomic<uint64_t> events{0};  // submissions + completions, written under mu
+  std::atomic<bool> spinner{false};
+  std::atomic<bool> stopping{false};
 
   // Next admissible query (caller holds mu), or null.
   std::unique_ptr<Query> pick() {
@@ -1577,20 +1758,41 @@ struct hpm_server {
                     hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     for (;;) {
       std::unique_ptr<Query> q;
+      bool spin = false;
+      uint64_t seen = 0;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv_work.wait(lk, [&] {
           if (stop && queue.empty()) return true;
           q = pick();
-          return q != nullptr;
+          if (q) return true;
+          // nobody polls for arrivals: this worker takes the role
+          bool no = false;
+          spin = spinner.compare_exchange_strong(no, true);
+          seen = events.load(std::memory_order_relaxed);
+          return spin;
         });
-        if (!q) break;
-        in_use += q->grant;
-        peak_in_use = std::max(peak_in_use, in_use);
-        running++;
-        peak_running = std::max(peak_running, running);
-        admitted++;
+        if (!q && !spin) break;  // stopping with an empty queue
+        if (q) {
+          // admitted: its grant is taken under the same lock that picked it
+          in_use += q->grant;
+          peak_in_use = std::max(peak_in_use, in_use);
+          running++;
+          peak_running = std::max(peak_running, running);
+          admitted++;
+        }
       }
+      if (!q) {
+        // poll until a query arrives or one finishes (it may make a queued
+        // one admissible) or the server stops; then give the role up and pick
+        while (events.load(std::memory_order_acquire) == seen &&
+               !stopping.load(std::memory_order_acquire))
+          __builtin_ia32_pause();
+        spinner.store(false, std::memory_order_release);
+        continue;
+      }
+      // this worker leaves the idle set: let a sleeper take over polling
+      cv_work.notify_one();
       const auto t0 = clock::now();
       int status = HPM_OK;
       uint64_t count = 0;
@@ -1619,6 +1821,7 @@ struct hpm_server {
         std::lock_guard<std::mutex> lk(mu);
         in_use -= q->grant;
         running--;
+        events.fetch_add(1, std::memory_order_release);
         Result& r = results[q->ticket];
         r.done = true;
         r.error = err;
@@ -2020,6 +2223,28 @@ int hpm_match_noalloc(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, 
   });
 }
 
+int hpm_scan_survivors(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
+                       const hpm_match_opts* opts, uint64_t* count, int32_t* rows,
+                       uint64_t cap) {
+  return guarded([&]() -> int {
+    if (!gc) fail(HPM_E_ARG, "graph is NULL");
+    if (!count) fail(HPM_E_ARG, "count is NULL");
+    uint32_t flags = 0;
+    uint64_t budget = 0, limit = 0;
+    read_opts(opts, &flags, &budget, &limit);
+    flags &= ~(uint32_t)(HPM_F_OVERLAP | HPM_F_LOOKAHEAD | HPM_F_COUNT_FROM_MAX);
+    const SurvivorsOut out{rows, rows ? cap : 0};
+    const int st = match_one(const_cast<hpm_graph*>(gc), p, (int)mode,
+                             static_cast<hipStream_t>(stream), flags, budget, count, nullptr, 0,
+                             &t_stats, nullptr, 0, &out);
+    if (st == HPM_OK && rows && *count > cap) {
+      t_error = "survivors " + std::to_string(*count) + " exceed cap " + std::to_string(cap);
+      return HPM_E_TRUNCATED;
+    }
+    return st;
+  });
+}
+
 int hpm_match(const hpm_graph* gc, const hpm_pattern* p, hpm_mode mode, void* stream,
               const hpm_match_opts* opts, uint64_t* count, int32_t* mappings, uint64_t cap) {
   return guarded([&]() -> int {
@@ -2268,6 +2493,7 @@ int hpm_server_submit(hpm_server* S, const hpm_pattern* p, hpm_mode mode, int32_
       *ticket = q->ticket;
       S->results[q->ticket] = hpm_server::Result{};
       S->queue.push_back(std::move(q));
+      S->events.fetch_add(1, std::memory_order_release);
     }
     S->cv_work.notify_one();
     return HPM_OK;
@@ -2323,6 +2549,7 @@ int hpm_server_destroy(hpm_server* S) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->stop = true;
     }
+    S->stopping.store(true, std::memory_order_release);
     S->cv_work.notify_all();
     for (std::thread& t : S->threads) t.join();
     delete S;

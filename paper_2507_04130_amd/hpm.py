@@ -12,7 +12,9 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhpm.so")
+# HPM_LIBRARY: load another build of the same sources (e.g. a sanitizer build)
+LIB_PATH = os.environ.get("HPM_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libhpm.so")
 
 OK, E_ARG, E_GRAPH, E_PATTERN, E_NOMEM, E_TRUNCATED, E_OVERFLOW, E_DEVICE, E_UNSUPPORTED, \
     E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
@@ -20,11 +22,13 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
-ABI_VERSION = 6  # HPM_ABI_VERSION of include/hpm.h
+ABI_VERSION = 8  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
 F_LOOKAHEAD = 0x10
+F_COUNT_FROM_MAX = 0x20
+F_NO_ARC_INDEX = 0x40
 
 
 def F_TIMING_KINDS(*names):
@@ -39,7 +43,7 @@ KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand",
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-           "hpm_match_noalloc", "hpm_match_batch",
+           "hpm_match_noalloc", "hpm_scan_survivors", "hpm_match_batch",
            "hpm_batch_tune", "hpm_match_batch_persistent", "hpm_batch_autotune",
            "hpm_last_batch_stats",
            "hpm_server_create", "hpm_server_submit", "hpm_server_poll", "hpm_server_read_stats",
@@ -76,7 +80,7 @@ class _Stats(ctypes.Structure):
                 ("overlap_removed", ctypes.c_uint64), ("counted_rows", ctypes.c_uint64),
                 ("counted_work", ctypes.c_uint64), ("filter_rows", ctypes.c_uint64),
                 ("filter_entries", ctypes.c_uint64), ("filter_pieces", ctypes.c_uint64),
-                ("lookahead_removed", ctypes.c_uint64)]
+                ("lookahead_removed", ctypes.c_uint64), ("index_arcs", ctypes.c_uint64)]
 
 
 X_MAPPED, X_SHORTER = 0, 1
@@ -145,6 +149,8 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(U64)]
     lib.hpm_match.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
                               ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
+    lib.hpm_scan_survivors.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
+                                       ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
     lib.hpm_match_noalloc.argtypes = [P, ctypes.POINTER(_Pattern), ctypes.c_int, P,
                                       ctypes.POINTER(_Opts), ctypes.POINTER(U64), P, U64]
     lib.hpm_match_batch.argtypes = [P, I32, ctypes.POINTER(_Pattern), P, P, ctypes.POINTER(_Opts),
@@ -171,7 +177,7 @@ def load() -> ctypes.CDLL:
     lib.hpm_last_error.restype = ctypes.c_char_p
     lib.hpm_abi_version.restype = ctypes.c_int
     for name in ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",
-                 "hpm_match_noalloc",
+                 "hpm_match_noalloc", "hpm_scan_survivors",
                  "hpm_match_batch", "hpm_batch_tune", "hpm_match_batch_persistent",
                  "hpm_batch_autotune", "hpm_last_batch_stats",
                  "hpm_server_create", "hpm_server_submit", "hpm_server_poll",
@@ -339,6 +345,26 @@ def match_noalloc(g: Graph, p, mode: int, out=None, stream=None, budget: int | N
     _check(lib.hpm_match_noalloc(g.handle, ctypes.byref(s), int(mode), _stream_handle(stream),
                                  ctypes.byref(opts), ctypes.byref(cnt), ptr, cap))
     return int(cnt.value), (out[: int(cnt.value)] if out is not None else None)
+
+
+def scan_survivors(g: Graph, p, mode: int, stream=None, flags: int = 0):
+    """hpm_scan_survivors: the depth-2 rows (image of position 0, image of
+    position 1) that pass the validators (deterministic but unspecified
+    order), as an int32 [s2, 2] torch tensor on the current device."""
+    import torch
+    lib = load()
+    _check_columns(g, p)
+    s, keep = _pattern_struct(p)
+    opts = _Opts(ctypes.sizeof(_Opts), flags, 0, 0)
+    cnt = ctypes.c_uint64()
+    sh = _stream_handle(stream)
+    _check(lib.hpm_scan_survivors(g.handle, ctypes.byref(s), int(mode), sh, ctypes.byref(opts),
+                                  ctypes.byref(cnt), None, 0))
+    buf = torch.empty((max(int(cnt.value), 1), 2), dtype=torch.int32, device="cuda")
+    _check(lib.hpm_scan_survivors(g.handle, ctypes.byref(s), int(mode), sh, ctypes.byref(opts),
+                                  ctypes.byref(cnt), ctypes.c_void_p(buf.data_ptr()),
+                                  int(buf.shape[0])))
+    return buf[: int(cnt.value)]
 
 
 def match_batch(g: Graph, patterns, modes, workers: int = 0, stream=None,
@@ -543,6 +569,7 @@ def last_stats() -> dict:
         "counted_rows": s.counted_rows, "counted_work": s.counted_work,
         "filter_rows": s.filter_rows, "filter_entries": s.filter_entries,
         "filter_pieces": s.filter_pieces, "lookahead_removed": s.lookahead_removed,
+        "index_arcs": s.index_arcs,
     }
 
 

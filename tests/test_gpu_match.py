@@ -511,3 +511,134 @@ def test_lookahead_changes_nothing():
         c1, _ = hpm.match(dc, p, MONO, flags=hpm.F_LOOKAHEAD)
         assert c1 == want.count, p.name
     dc.close()
+
+
+def _pred_ok(op, val, x):
+    x = np.asarray(x)
+    if op == 0:
+        return np.ones(x.shape, dtype=bool)
+    return (x == val) if op == 1 else (x >= val)
+
+
+def _validator_survivors(g, p, mode, o0, o1):
+    """Depth-2 rows the validators must keep, from their definitions (Alg. 2,
+    Alg. 3 with the reverse-arc rule of Eq. (1)), with numpy over every arc."""
+    n, m = g.n, g.m
+    indeg, outdeg = np.diff(g.in_off), np.diff(g.out_off)
+    arcs = list(p.arcs())
+    pin = [sum(1 for a, b in arcs if b == v) for v in range(p.k)]
+    pout = [sum(1 for a, b in arcs if a == v) for v in range(p.k)]
+
+    def vv(a):
+        ok = (indeg >= pin[a]) & (outdeg >= pout[a])
+        for c in range(len(g.vcols)):
+            ok &= _pred_ok(int(p.vop[a, c]), int(p.vval[a, c]), g.vcols[c])
+        return ok
+
+    def arc_pred(i, eids):
+        ok = np.ones(eids.shape, dtype=bool)
+        for c in range(len(g.ecols)):
+            ok &= _pred_ok(int(p.eop[i, c]), int(p.eval[i, c]), g.ecols[c][eids])
+        return ok
+
+    src = np.repeat(np.arange(n, dtype=np.int64), outdeg)
+    dst = g.out_nbrs.astype(np.int64)
+    eid = np.arange(m)
+    keys = src * n + dst
+    rev_key = dst * n + src
+    pos = np.searchsorted(keys, rev_key)
+    pos[pos >= m] = 0
+    rev = np.where(keys[pos] == rev_key, pos, -1)          # out-CSR id of the reverse arc
+    idx = {a: i for i, a in enumerate(arcs)}
+    if (o0, o1) in idx:        # target arc x -> y is the image of o0 -> o1
+        f0, f1, fwd_i, back = src, dst, idx[(o0, o1)], idx.get((o1, o0))
+    else:                      # only o1 -> o0: target arc x -> y is its image
+        f0, f1, fwd_i, back = dst, src, idx[(o1, o0)], None
+    ok = vv(o0)[f0] & vv(o1)[f1] & arc_pred(fwd_i, eid)
+    if back is not None:
+        ok &= rev >= 0
+        ok[ok] &= arc_pred(back, rev[ok])
+    elif mode == ISO:
+        ok &= rev < 0
+    return np.stack([f0[ok], f1[ok]], axis=1).astype(np.int32)
+
+
+def test_scan_survivors_equal_the_validator_definitions():
+    # the vertex and edge validators (Sec. III-B, Alg. 2-3) as a stage: the
+    # depth-2 rows equal, as a set, a numpy filter written from their
+    # definitions, and every oracle embedding's images of positions 0 and 1
+    # are among them (the validators only remove what cannot extend)
+    graphs = [("rmat10", rmat(10, 1 << 13, seed=61)),
+              ("connectome", configs.c3_graph(n=20_000, m=150_000))]
+    rng = np.random.default_rng(4242)
+    for gname, g in graphs:
+        dg = hpm.Graph.from_host(g)
+        if gname == "rmat10":
+            cases = [(p, m) for p in configs.c2_patterns() for m in (ISO, MONO)]
+            for i in range(8):
+                cases.append((random_pattern(rng, kmin=2, kmax=6), ISO if i % 2 else MONO))
+        else:
+            cases = [(p, MONO) for p in configs.c3_patterns()]
+            cases += [(p, ISO) for p in configs.c3_patterns()]
+        for p, mode in cases:
+            order = hpm.plan_order(p, len(g.vcols), len(g.ecols))
+            want = _validator_survivors(g, p, mode, order[0], order[1])
+            got = hpm.scan_survivors(dg, p, mode).cpu().numpy()
+            np.testing.assert_array_equal(lexsorted(got), lexsorted(want),
+                                          err_msg=f"{gname} {p.name} {mode}")
+            res = oracle.match(g, p, mode, threads=8, rows=True) if p.k <= 5 else None
+            if res is not None and res.count:
+                pairs = {(int(a), int(b)) for a, b in want}
+                need = {(int(r[order[0]]), int(r[order[1]])) for r in res.rows}
+                assert need <= pairs, f"{gname} {p.name}: a validator dropped an embedding"
+            say(f"{gname} {p.name}/{mode}: {len(got)} survivors")
+        dg.close()
+
+
+def test_count_wrap_is_reported():
+    # a running count that starts at 2^64 - 1 (test-only flag) wraps on the
+    # first embedding: the call fails with HPM_E_OVERFLOW
+    g = rmat(10, 1 << 13, seed=61)
+    dg = hpm.Graph.from_host(g)
+    for p, mode in ((motif("cycle3"), MONO), (motif("ffl_tail"), ISO), (motif("cycle4"), MONO)):
+        c, _ = hpm.match(dg, p, mode)
+        assert c > 0
+        with pytest.raises(hpm.HpmError) as e:
+            hpm.match(dg, p, mode, flags=hpm.F_COUNT_FROM_MAX)
+        assert e.value.status == hb.E_OVERFLOW, p.name
+    dg.close()
+
+
+def test_arc_index_changes_nothing():
+    # monomorphism queries whose arcs all carry a predicate read adjacency
+    # restricted to the arcs that pass the loosest of them: counts and rows
+    # equal the oracle's and the unrestricted run's, with several chunks too,
+    # and the index is built where the predicate is selective
+    g = configs.c3_graph(n=20_000, m=150_000)
+    dg = hpm.Graph.from_host(g)
+    rng = np.random.default_rng(5150)
+    cases = list(configs.c3_patterns())
+    for i in range(10):
+        cases.append(random_pattern(rng, kmin=3, kmax=6, vlabels=("uniform", 8), eop=GE,
+                                    eval_const=int(rng.integers(3, 12))))
+    built = 0
+    for p in cases:
+        want = oracle.match(g, p, MONO, threads=8)
+        for flags, budget in ((0, None), (hpm.F_NO_ARC_INDEX, None), (0, 4 << 20),
+                              (hpm.F_LOOKAHEAD, None)):
+            cnt, _ = hpm.match(dg, p, MONO, flags=flags, budget=budget)
+            st = hpm.last_stats()
+            if flags == 0 and budget is None:
+                built += st["index_arcs"] > 0
+            assert cnt == want.count, (p.name, flags, budget)
+        if want.count <= 2_000_000:
+            _, rows = gpu_rows(dg, p, MONO)
+            np.testing.assert_array_equal(rows, want.rows, err_msg=p.name)
+        say(f"arc index {p.name}: {want.count} embeddings, index arcs {st['index_arcs']}")
+    assert built >= 3
+    # induced isomorphism never uses it (non-arcs need the whole graph)
+    p = configs.c3_patterns()[0]
+    cnt, _ = hpm.match(dg, p, ISO)
+    assert hpm.last_stats()["index_arcs"] == 0
+    assert cnt == oracle.match(g, p, ISO, threads=8, rows=False).count
+    dg.close()
