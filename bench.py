@@ -91,7 +91,8 @@ def workload(name):
 
 def kernel_bytes(stats_list, g, runs):
     """Algorithmic bytes per kernel family, summed over the given match calls."""
-    out = {"vertex_validator": 0, "edge_scan": 0, "expand": 0, "last_level": 0, "filter": 0}
+    out = {"vertex_validator": 0, "edge_scan": 0, "expand": 0, "last_level": 0, "filter": 0,
+           "index": 0}
     for st, (p, _) in zip(stats_list, runs):
         k = p.k
         out["vertex_validator"] += B_VERTEX * g.n
@@ -105,6 +106,13 @@ def kernel_bytes(stats_list, g, runs):
         # the filtered depths are not recorded per depth: take the deepest
         # row width as an upper bound of the images per row
         out["filter"] += (48 + 8 * (k - 1)) * st["filter_rows"] + 8 * st["filter_entries"]
+        # arc-predicate index, per side (out and in): the flag pass reads the
+        # column and writes a position (8 B per arc), the prefix scan reads the
+        # positions twice and writes them once (12 B), the compaction reads
+        # position, target and column (12 B) and writes each kept arc with its
+        # column (8 B), the offsets read, gather and write (12 B per vertex)
+        if st.get("index_arcs"):
+            out["index"] += 2 * (32 * g.m + 8 * st["index_arcs"] + 12 * (g.n + 1))
     return out
 
 
@@ -250,10 +258,13 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
             tickets.append(srv.submit(p, mode))
             if i % 500 == 499:
                 log(f"  {kind} {qps} q/s: {i + 1} of {n} submitted")
+        q_ms, r_ms = [], []
         for i, t in enumerate(tickets):
             r = srv.poll(t, wait=True)
             assert r["status"] == 0, r
             got[i] = r["count"]
+            q_ms.append(r["queue_ms"])
+            r_ms.append(r["run_ms"])
             lat[i] = late[i] + (r["queue_ms"] + r["run_ms"]) / 1000.0
         st = srv.stats()
         assert st["admitted"] - admitted0 == n
@@ -276,11 +287,18 @@ def serve_trace(hpm, dg, runs, expected, qps, n, kind, srv, stream):
     assert not bad, f"{kind} counts differ from the oracle's at {bad[:8]}"
     span = float(done[warm:].max() - arrivals[warm])
     matches = int(sum(expected[idx[i]] for i in range(warm, n)))
-    out = {"p50_ms": 1000.0 * float(np.percentile(lat[warm:], 50)),
+    out = {}
+    if kind == "served":
+        qms = np.array(q_ms[warm:])
+        rms = np.array(r_ms[warm:])
+        out.update({"queue_ms_p50": float(np.percentile(qms, 50)),
+                    "run_ms_p50": float(np.percentile(rms, 50)),
+                    "late_ms_p50": 1000.0 * float(np.percentile(late[warm:], 50))})
+    out.update({"p50_ms": 1000.0 * float(np.percentile(lat[warm:], 50)),
            "p99_ms": 1000.0 * float(np.percentile(lat[warm:], 99)),
            "mean_ms": 1000.0 * float(lat[warm:].mean()),
            "queries_per_sec": (n - warm) / span, "matches_per_sec": matches / span,
-           "matches": matches, "span_s": span, "measured": n - warm}
+           "matches": matches, "span_s": span, "measured": n - warm})
     if st:
         out["peak_running_so_far"] = st["peak_running"]
         out["peak_granted_gib_so_far"] = round(st["peak_granted_bytes"] / 2**30, 3)
@@ -481,7 +499,8 @@ def main():
         for st in prof_stats:
             for kname, ms in st["kernel_ms"].items():
                 prof_ms[kname] = prof_ms.get(kname, 0.0) + ms
-        costed_kinds = ("vertex_validator", "edge_scan", "expand", "last_level", "filter")
+        costed_kinds = ("vertex_validator", "edge_scan", "expand", "last_level", "filter",
+                        "index")
         dom_kind = max(costed_kinds, key=lambda k: prof_ms.get(k, 0.0))
         timed_flags = hpm.F_TIMING | hpm.F_TIMING_KINDS(dom_kind, "edge_scan")
         log(f"profile step: {({k: round(v, 3) for k, v in prof_ms.items() if v})}; "

@@ -43,7 +43,8 @@ extern "C" {
 /* 6: HPM_F_LOOKAHEAD, hpm_match_stats.lookahead_removed. */
 /* 7: hpm_scan_survivors, HPM_F_COUNT_FROM_MAX. */
 /* 8: HPM_F_NO_ARC_INDEX, hpm_match_stats.index_arcs. */
-#define HPM_ABI_VERSION 8
+/* 9: HPM_K_INDEX (HPM_K_NUM = 9). */
+#define HPM_ABI_VERSION 9
 #define HPM_MAX_K 16   /* largest pattern, in vertices            */
 #define HPM_MAX_COLS 4 /* largest number of vertex or arc columns */
 
@@ -137,7 +138,7 @@ typedef struct {
  * families whose bit (1 << HPM_K_*) is set in mask; mask 0 = every family.
  * Each timed launch costs two event records on the stream, so timing a few
  * families disturbs the call less than timing all of them. */
-#define HPM_F_TIMING_KINDS(mask) ((((uint32_t)(mask)) & 0xffu) << 16)
+#define HPM_F_TIMING_KINDS(mask) ((((uint32_t)(mask)) & 0x1ffu) << 16)
 #define HPM_F_NO_FILTER 0x4u  /* do not pre-filter long shared candidate lists \
                                  (same result; for checking and measurement) */
 #define HPM_F_OVERLAP 0x8u    /* apply the edge validator's neighbour-overlap  \
@@ -479,8 +480,10 @@ enum {
   HPM_K_EXPAND = 4,           /* extend partial mappings by one vertex               */
   HPM_K_LAST_LEVEL = 5,       /* final vertex: count (and write mappings)            */
   HPM_K_REDUCE = 6,           /* per-block counts -> total                           */
-  HPM_K_FILTER = 7,           /* pre-filtering of long shared candidate lists        */
-  HPM_K_NUM = 8
+  HPM_K_FILTER = 7,           /* pre-filtering of long shared candidate lists,       */
+                              /* look-ahead and overlap passes                       */
+  HPM_K_INDEX = 8,            /* arc-predicate index (restricted adjacency)          */
+  HPM_K_NUM = 9
 };
 
 /* Per-call statistics of the calling thread's most recent successful hpm_match.

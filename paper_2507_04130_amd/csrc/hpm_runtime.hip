@@ -548,7 +548,7 @@ struct Matcher {
   bool timing;
   bool filter;
   int max_grid;
-  uint32_t timed_kinds = 0xffu;  // families timed when timing (bit = HPM_K_*)
+  uint32_t timed_kinds = 0x1ffu;  // families timed when timing (bit = HPM_K_*)
   int64_t cap2 = 0;     // depth-2 rows per arc chunk
   int64_t chunk = 0;    // rows per frontier chunk at depth >= 3
   uint64_t budget = 0;  // scratch limit of the call
@@ -558,6 +558,8 @@ struct Matcher {
   int32_t overlap_need = 0;   // common neighbours of positions 0 and 1 (overlap test on)
   bool lookahead = false;     // frontier look-ahead on the rows of every depth
   bool indexed = false;       // g reads the arc-predicate index
+  bool want_index = false;    // consider the index once the first arc chunk is scanned
+  uint32_t call_flags = 0;
   // survivors only: the depth-2 rows after the validators are copied to
   // surv_out ([surv_cap][2], positions 0 and 1) and nothing is extended
   int32_t* surv_out = nullptr;
@@ -769,11 +771,7 @@ struct Matcher {
     int t_use = -1;
     for (int t = 2; t >= 1 && t_use < 0; --t)
       if (masks[t] && 2 * distinct[t] <= r && groups(t)) t_use = t;
-    // Grouping by pivot list alone filters a list by the validator and the
-    // pivot arc's predicate; over the arc-predicate index the predicate holds
-    // already and the pass costs more than it removes (connectome: 10% of the
-    // candidates for 19 ms per step), so it is left out there.
-    if (t_use < 0 && !indexed && groups(0)) t_use = 0;
+    if (t_use < 0 && groups(0)) t_use = 0;
     const uint32_t use_mask = t_use > 0 ? masks[t_use] : 0u;
     if (nslots == 0) return;
     // Long lists are split over several blocks (pieces of kFilterPiece
@@ -1121,7 +1119,7 @@ struct Matcher {
       cols_in[c] = G->ecols_in[c].as<int32_t>();
     }
     // out side: positions, the number of passing arcs, then the arrays
-    launch(HPM_K_FILTER, [&] {
+    launch(HPM_K_INDEX, [&] {
       return hpm::launch_arc_index_flags(cols_out, lo, hi, cmask, m, pos,
                                          W->absum.as<int64_t>(), stream);
     });
@@ -1141,18 +1139,18 @@ struct Matcher {
       co[c] = W->acol_out[c].as<int32_t>();
       ci[c] = W->acol_in[c].as<int32_t>();
     }
-    launch(HPM_K_FILTER, [&] {
+    launch(HPM_K_INDEX, [&] {
       return hpm::launch_arc_index_fill(G->out_off.as<int32_t>(), G->n,
                                         G->out_nbrs.as<int32_t>(), cols_out, nc, lo, hi, cmask, m,
                                         pos, W->aoff_out.as<int32_t>(),
                                         W->anbrs_out.as<int32_t>(), co, stream);
     });
     // in side (the transpose: the same arcs pass)
-    launch(HPM_K_FILTER, [&] {
+    launch(HPM_K_INDEX, [&] {
       return hpm::launch_arc_index_flags(cols_in, lo, hi, cmask, m, pos,
                                          W->absum.as<int64_t>(), stream);
     });
-    launch(HPM_K_FILTER, [&] {
+    launch(HPM_K_INDEX, [&] {
       return hpm::launch_arc_index_fill(G->in_off.as<int32_t>(), G->n, G->in_nbrs.as<int32_t>(),
                                         cols_in, nc, lo, hi, cmask, m, pos,
                                         W->aoff_in.as<int32_t>(), W->anbrs_in.as<int32_t>(), ci,
@@ -1237,6 +1235,23 @@ struct Matcher {
       const int64_t s2 = read_i64(cnt + grid);
       if (s2 > e1 - e0) fail(HPM_E_INTERNAL, "scan overflow");
       st.survivors += (uint64_t)s2;
+      if (want_index) {
+        // The index costs a few passes over every arc; it pays when the
+        // frontier is large (here: depth-2 rows, scaled to the whole graph,
+        // at least 1/256 of the arcs).
+        want_index = false;
+        if ((double)s2 * (double)m / (double)(e1 - e0) >= (double)m / 256.0) {
+          build_arc_index(call_flags);
+          if (indexed) {
+            // degrees counted over the index only: a stronger validator for
+            // the later positions (and for the scan of later arc chunks)
+            launch(HPM_K_VERTEX_VALIDATOR, [&] {
+              return hpm::launch_vertex_validator(g, dplan(), W->vbits.as<uint32_t>(),
+                                                  bit_words(), stream);
+            });
+          }
+        }
+      }
       if (s2 == 0) continue;
       need(W->rows2d, (size_t)s2 * 2 * sizeof(int32_t));
       ensure_depth(2, s2);
@@ -1567,7 +1582,7 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
 
     Matcher M{G, W, stream, G->view(), G->view(), plan, k, mappings, mappings ? cap : 0,
               (flags & HPM_F_TIMING) != 0, (flags & HPM_F_NO_FILTER) == 0, max_grid};
-    M.timed_kinds = (flags >> 16) & 0xffu ? (flags >> 16) & 0xffu : 0xffu;
+    M.timed_kinds = (flags >> 16) & 0x1ffu ? (flags >> 16) & 0x1ffu : 0x1ffu;
     M.cap2 = cap2;
     M.chunk = chunk;
     M.budget = budget;
@@ -1609,7 +1624,8 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       M.surv_out = surv->rows;
       M.surv_cap = surv->cap;
     } else {
-      M.build_arc_index(flags);
+      M.call_flags = flags;
+      M.want_index = true;
     }
     M.run();
     M.sync();

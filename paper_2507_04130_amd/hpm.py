@@ -22,7 +22,7 @@ PENDING = 1
 ISO, MONO = 0, 1
 ANY, EQ, GE = 0, 1, 2
 F_NO_REORDER = 0x1
-ABI_VERSION = 8  # HPM_ABI_VERSION of include/hpm.h
+ABI_VERSION = 9  # HPM_ABI_VERSION of include/hpm.h
 F_TIMING = 0x2
 F_NO_FILTER = 0x4
 F_OVERLAP = 0x8
@@ -36,10 +36,10 @@ def F_TIMING_KINDS(*names):
     mask = 0
     for n in names:
         mask |= 1 << KERNELS.index(n)
-    return (mask & 0xFF) << 16
+    return (mask & 0x1FF) << 16
 MAX_K = 16
 KERNELS = ("vertex_validator", "edge_scan", "row_pivot", "prefix_sum", "expand", "last_level",
-           "reduce", "filter")
+           "reduce", "filter", "index")
 
 # Every function include/hpm.h declares.
 EXPORTS = ("hpm_graph_create", "hpm_graph_destroy", "hpm_graph_info", "hpm_match",

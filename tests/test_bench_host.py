@@ -29,6 +29,10 @@ def test_kernel_bytes_follow_the_per_unit_figures():
     assert out["expand"] == bench.B_CAND * 300 + 4 * 3 * 40
     assert out["last_level"] == bench.B_CAND * (900 - 200) + (4 * 3 + 24 + 4 * 3) * 10
     assert out["filter"] == (48 + 8 * 3) * 50 + 8 * 600
+    assert out["index"] == 0
+    st["index_arcs"] = 1200
+    idx = bench.kernel_bytes([st], _G, [(p, MONO)])["index"]
+    assert idx == 2 * (32 * _G.m + 8 * 1200 + 12 * (_G.n + 1))
     # a three-vertex pattern goes from depth 2 straight to the last level
     p3 = motif("cycle3")
     three = bench.kernel_bytes([_stats(5, [0, 0, 40, 0], [0, 0, 5, 0])], _G, [(p3, MONO)])
