@@ -205,19 +205,34 @@ hipError_t launch_lookahead_filter(const DevGraph& g, const DevPlan* plan, const
                                    int64_t words, const int32_t* rows, int64_t n, int32_t d,
                                    uint32_t fmask, int32_t* out, unsigned long long* cursor,
                                    hipStream_t stream);
-// Arc-predicate index (adjacency restricted to the arcs whose columns in
-// cmask lie in [lo[c], hi[c]]).  flags: pos[0..m] = exclusive prefix counts of
-// the passing arcs (pos[m] = their number); bsum needs ceil((m + 1) / 4096)
-// + 2 entries.  fill: off_out[0..n] = pos[off[v]], the passing arcs' targets
-// into nbrs_out and their first ncols columns into cols_out (rows stay sorted).
-hipError_t launch_arc_index_flags(const int32_t* const* cols, const int32_t* lo,
-                                  const int32_t* hi, uint32_t cmask, int64_t m, int32_t* pos,
-                                  int64_t* bsum, hipStream_t stream);
-hipError_t launch_arc_index_fill(const int32_t* off, int32_t n, const int32_t* nbrs,
-                                 const int32_t* const* cols, int32_t ncols, const int32_t* lo,
-                                 const int32_t* hi, uint32_t cmask, int64_t m, const int32_t* pos,
-                                 int32_t* off_out, int32_t* nbrs_out, int32_t* const* cols_out,
-                                 hipStream_t stream);
+// Arc-predicate index: adjacency restricted to the arcs whose columns in
+// cmask lie in [lo[c], hi[c]], built for both CSR sides at once (s[0] the
+// out side, s[1] the in side).  Per side: mask and wpre hold
+// arc_index_words(m) entries, bsum arc_index_tiles(m) + 1.
+struct ArcIndexSide {
+  const int32_t* off;                // n + 1 row offsets
+  const int32_t* nbrs;               // m targets
+  const int32_t* cols[kMaxCols];     // m values per column
+  uint64_t* mask;                    // pass bits, 64 arcs per word
+  int32_t* wpre;                     // passing arcs before each word
+  int64_t* bsum;                     // per-tile counts, then their prefix
+  int32_t* off_out;                  // n + 1
+  int32_t* nbrs_out;                 // cap
+  int32_t* cols_out[kMaxCols];       // cap each (the first ncols)
+};
+struct ArcIndexSides {
+  ArcIndexSide s[2];
+};
+int64_t arc_index_tiles(int64_t m);
+int64_t arc_index_words(int64_t m);
+// count: pass bits and tile prefixes of both sides; totals[side] = the number
+// of passing arcs (equal for a consistent graph).
+hipError_t launch_arc_index_count(const ArcIndexSides& S, const int32_t* lo, const int32_t* hi,
+                                  uint32_t cmask, int64_t m, int64_t* totals, hipStream_t stream);
+// fill: off_out[0..n] and the passing arcs' targets and first ncols columns,
+// in arc order (rows stay sorted); ranks at or past cap are dropped.
+hipError_t launch_arc_index_fill(const ArcIndexSides& S, int32_t n, int32_t ncols, int64_t m,
+                                 int64_t cap, hipStream_t stream);
 // Blocks for an arc scan over `arcs` arcs with out_mode 0 or 1 (one per tile).
 int64_t edge_scan_blocks(int64_t arcs);
 // Pivot choice and candidate-list length of every row at depth d; writes piv[r]

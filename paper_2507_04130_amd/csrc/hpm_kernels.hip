@@ -1833,10 +1833,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_counts(const unsigned long lo
 // ------------------------------------------------------------ arc-predicate index
 //
 // Adjacency restricted to the arcs that pass one attribute predicate (every
-// column c in cmask within [lo[c], hi[c]]): pos[e] = 1 for a passing arc e
-// (0 otherwise, pos[m] = 0), an exclusive scan turns pos into the new index
-// of every arc, then the passing arcs and their columns are compacted and the
-// row offsets become off'[v] = pos[off[v]].  Rows stay sorted.
+// column c in cmask within [lo[c], hi[c]]), built for the out- and the in-CSR
+// in the same launches (blockIdx.y is the side).  A tile of kArcTile arcs per
+// block, one 64-bit word of pass bits per 64 arcs:
+//   mask:    bits and per-tile counts (reads the predicate columns once);
+//   scan:    exclusive scan of the tile counts (one block per side);
+//   compact: word prefixes (kept for the offsets), then every passing arc's
+//            target and columns to its rank among the passing arcs;
+//   offsets: off'[v] = the passing arcs before off[v], from the word prefix
+//            and a popcount.
+// Rows stay sorted.  The mask and prefix arrays hold arc_index_words(m)
+// entries per side; the last is one past every tile (zero bits, prefix =
+// the total), so off[n] = m maps to the total whatever m is.
 struct ArcPred {
   int32_t lo[kMaxCols], hi[kMaxCols];
   uint32_t cmask;
@@ -1854,78 +1862,107 @@ __device__ __forceinline__ bool arc_pred_ok(const int32_t* const* cols, const Ar
   return ok;
 }
 
-struct ColPtrs {
-  const int32_t* c[kMaxCols];
-};
-struct ColOut {
-  int32_t* c[kMaxCols];
-};
+constexpr int kArcTileWords = kBlock;  // one word per thread
+constexpr int64_t kArcTile = (int64_t)kArcTileWords * 64;
 
-__global__ __launch_bounds__(kBlock) void k_arc_flags(ColPtrs cols, ArcPred P, int64_t m,
-                                                      int32_t* __restrict__ pos) {
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e <= m;
-       e += (int64_t)gridDim.x * kBlock)
-    pos[e] = (e < m && arc_pred_ok(cols.c, P, e)) ? 1 : 0;
-}
-
-constexpr int kI32ScanItems = 16;
-constexpr int kI32ScanTile = kBlock * kI32ScanItems;
-
-// Per-block sums of int32 values a[0..len), blocks of kI32ScanTile entries.
-__global__ __launch_bounds__(kBlock) void k_i32_block_sums(const int32_t* __restrict__ a,
-                                                           int64_t len,
-                                                           int64_t* __restrict__ bsum) {
+// m > 0.  Loads are unconditional (the index clamped to the last arc) and
+// issued in batches, so a wave keeps many in flight.
+__global__ __launch_bounds__(kBlock) void k_arc_mask(ArcIndexSides S, ArcPred P, int64_t m) {
+  const ArcIndexSide& sd = S.s[blockIdx.y];
   __shared__ int64_t s_scan[kWaves + 1];
-  const int64_t base = (int64_t)blockIdx.x * kI32ScanTile + (int64_t)threadIdx.x * kI32ScanItems;
-  int64_t s = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave w fills words w*64 .. w*64+63 of the tile; lane j keeps word j
+  const int64_t word0 = (int64_t)blockIdx.x * kArcTileWords + wave * 64;
+  const int64_t e0 = word0 * 64 + lane;  // this lane's arc in word j: e0 + 64 j
+  uint64_t okm = ~0ull;                  // bit j: that arc passes every column so far
+  for (int c = 0; c < kMaxCols; ++c) {
+    if (!((P.cmask >> c) & 1u)) continue;
+    const int32_t* __restrict__ col = sd.cols[c];
+    const int32_t lo = P.lo[c], hi = P.hi[c];
+#pragma unroll 1
+    for (int j0 = 0; j0 < 64; j0 += 16) {
+      int32_t x[16];
 #pragma unroll
-  for (int i = 0; i < kI32ScanItems; ++i)
-    if (base + i < len) s += a[base + i];
-  const int64_t tot = block_sum<int64_t>(s, s_scan);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-// a[0..len) -> exclusive prefix sums, block offsets from the scanned bsum.
-__global__ __launch_bounds__(kBlock) void k_i32_scan_apply(int32_t* __restrict__ a, int64_t len,
-                                                           const int64_t* __restrict__ bsum) {
-  __shared__ int64_t s_scan[kWaves + 1];
-  const int64_t base = (int64_t)blockIdx.x * kI32ScanTile + (int64_t)threadIdx.x * kI32ScanItems;
-  int32_t v[kI32ScanItems];
-  int64_t s = 0;
+      for (int i = 0; i < 16; ++i) x[i] = col[min(e0 + 64 * (j0 + i), m - 1)];
 #pragma unroll
-  for (int i = 0; i < kI32ScanItems; ++i) {
-    v[i] = base + i < len ? a[base + i] : 0;
-    s += v[i];
+      for (int i = 0; i < 16; ++i)
+        if (x[i] < lo || x[i] > hi) okm &= ~(1ull << (j0 + i));
+    }
   }
+  uint64_t mine = 0;
+  int64_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    const uint64_t bits = __ballot(((okm >> j) & 1ull) && e0 + 64 * j < m);
+    mine = lane == j ? bits : mine;
+    cnt += __popcll(bits);
+  }
+  sd.mask[word0 + lane] = mine;
+  const int64_t tot = block_sum<int64_t>(lane == 0 ? cnt : 0, s_scan);
+  if (threadIdx.x == 0) {
+    sd.bsum[blockIdx.x] = tot;
+    if (blockIdx.x == 0) sd.mask[(int64_t)gridDim.x * kArcTileWords] = 0;
+  }
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), j) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+}
+
+// Copies 8 words' worth of one array (arcs e0 + 64 j, j = j0 .. j0 + 7) to the
+// ranks in at (-1: the arc does not pass).
+__device__ __forceinline__ void arc_copy8(const int32_t* __restrict__ src,
+                                          int32_t* __restrict__ dst, int64_t e0, int j0,
+                                          int64_t m, const int64_t (&at)[8]) {
+  int32_t x[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) x[i] = src[min(e0 + 64 * (j0 + i), m - 1)];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (at[i] >= 0) dst[at[i]] = x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_arc_compact(ArcIndexSides S, int32_t ncols,
+                                                        int64_t m, int64_t cap) {
+  const ArcIndexSide& sd = S.s[blockIdx.y];
+  __shared__ int64_t s_scan[kWaves + 1];
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * kArcTileWords + threadIdx.x;
+  const uint64_t bits = sd.mask[w];
   int64_t tot;
-  int64_t run = block_exclusive_scan<int64_t>(s, s_scan, &tot) + bsum[blockIdx.x];
+  const int64_t pre =
+      block_exclusive_scan<int64_t>(__popcll(bits), s_scan, &tot) + sd.bsum[blockIdx.x];
+  sd.wpre[w] = (int32_t)pre;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    sd.wpre[(int64_t)gridDim.x * kArcTileWords] = (int32_t)sd.bsum[gridDim.x];
+  // the wave's 64 words, eight at a time: lane l handles arc 64 * word + l
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t e0 = (w - lane) * 64 + lane;
+  const int32_t pre32 = (int32_t)pre;
+#pragma unroll 1
+  for (int j0 = 0; j0 < 64; j0 += 8) {
+    int64_t at[8];
 #pragma unroll
-  for (int i = 0; i < kI32ScanItems; ++i) {
-    if (base + i < len) a[base + i] = (int32_t)run;
-    run += v[i];
+    for (int i = 0; i < 8; ++i) {
+      const uint64_t b = readlane64(bits, j0 + i);
+      const int64_t r = (int64_t)__builtin_amdgcn_readlane(pre32, j0 + i) + __popcll(b & below);
+      // ranks at or past cap: a side whose arcs disagree with the sized total
+      at[i] = ((b >> lane) & 1ull) && r < cap ? r : -1;
+    }
+    arc_copy8(sd.nbrs, sd.nbrs_out, e0, j0, m, at);
+    for (int c = 0; c < ncols; ++c) arc_copy8(sd.cols[c], sd.cols_out[c], e0, j0, m, at);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_arc_compact(const int32_t* __restrict__ nbrs,
-                                                        ColPtrs cols, ArcPred P, int32_t ncols,
-                                                        int64_t m, const int32_t* __restrict__ pos,
-                                                        int32_t* __restrict__ nbrs_out,
-                                                        ColOut cols_out) {
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * kBlock) {
-    if (pos[e + 1] == pos[e]) continue;  // the arc fails the predicate
-    const int32_t at = pos[e];
-    nbrs_out[at] = nbrs[e];
-    for (int c = 0; c < ncols; ++c) cols_out.c[c][at] = cols.c[c][e];
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_arc_offsets(const int32_t* __restrict__ off, int32_t n,
-                                                        const int32_t* __restrict__ pos,
-                                                        int32_t* __restrict__ off_out) {
+__global__ __launch_bounds__(kBlock) void k_arc_offsets(ArcIndexSides S, int32_t n) {
+  const ArcIndexSide& sd = S.s[blockIdx.y];
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v <= n;
-       v += (int64_t)gridDim.x * kBlock)
-    off_out[v] = pos[off[v]];
+       v += (int64_t)gridDim.x * kBlock) {
+    const int32_t o = sd.off[v];
+    const int64_t w = o >> 6;
+    sd.off_out[v] = sd.wpre[w] + __popcll(sd.mask[w] & ((1ull << (o & 63)) - 1ull));
+  }
 }
 
 inline int grid_for(int64_t items, int64_t per_block, int max_grid) {
@@ -2070,53 +2107,39 @@ hipError_t launch_row_pivot(const DevGraph& g, const DevPlan* plan, int32_t d,
   return hipGetLastError();
 }
 
-hipError_t launch_arc_index_flags(const int32_t* const* cols, const int32_t* lo,
-                                  const int32_t* hi, uint32_t cmask, int64_t m, int32_t* pos,
-                                  int64_t* bsum, hipStream_t stream) {
-  ColPtrs cp{};
+int64_t arc_index_tiles(int64_t m) { return std::max<int64_t>(1, (m + kArcTile - 1) / kArcTile); }
+int64_t arc_index_words(int64_t m) { return arc_index_tiles(m) * kArcTileWords + 1; }
+
+hipError_t launch_arc_index_count(const ArcIndexSides& S, const int32_t* lo, const int32_t* hi,
+                                  uint32_t cmask, int64_t m, int64_t* totals,
+                                  hipStream_t stream) {
   ArcPred P{};
   for (int c = 0; c < kMaxCols; ++c) {
-    cp.c[c] = cols[c];
     P.lo[c] = lo[c];
     P.hi[c] = hi[c];
   }
   P.cmask = cmask;
-  k_arc_flags<<<grid_for(m + 1, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(cp, P, m, pos);
+  if (m <= 0) return hipErrorInvalidValue;
+  const int nb = (int)arc_index_tiles(m);
+  k_arc_mask<<<dim3(nb, 2), kBlock, 0, stream>>>(S, P, m);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // exclusive scan of pos[0..m]: block sums, one-block scan of those, apply
-  const int64_t len = m + 1;
-  const int nb = (int)((len + kI32ScanTile - 1) / kI32ScanTile);
-  k_i32_block_sums<<<nb, kBlock, 0, stream>>>(pos, len, bsum);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_scan_bsum<<<1, kBlock, 0, stream>>>(bsum, nb, bsum + nb + 1, 0);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_i32_scan_apply<<<nb, kBlock, 0, stream>>>(pos, len, bsum);
-  return hipGetLastError();
+  for (int side = 0; side < 2 && e == hipSuccess; ++side) {
+    // tile offsets; the side's total also goes to totals[side]
+    k_scan_bsum<<<1, kBlock, 0, stream>>>(S.s[side].bsum, nb, totals, side);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
-hipError_t launch_arc_index_fill(const int32_t* off, int32_t n, const int32_t* nbrs,
-                                 const int32_t* const* cols, int32_t ncols, const int32_t* lo,
-                                 const int32_t* hi, uint32_t cmask, int64_t m, const int32_t* pos,
-                                 int32_t* off_out, int32_t* nbrs_out, int32_t* const* cols_out,
-                                 hipStream_t stream) {
-  ColPtrs cp{};
-  ColOut co{};
-  ArcPred P{};
-  for (int c = 0; c < kMaxCols; ++c) {
-    cp.c[c] = cols[c];
-    co.c[c] = cols_out[c];
-    P.lo[c] = lo[c];
-    P.hi[c] = hi[c];
-  }
-  P.cmask = cmask;
-  if (m > 0)
-    k_arc_compact<<<grid_for(m, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
-        nbrs, cp, P, ncols, m, pos, nbrs_out, co);
+hipError_t launch_arc_index_fill(const ArcIndexSides& S, int32_t n, int32_t ncols, int64_t m,
+                                 int64_t cap, hipStream_t stream) {
+  if (m <= 0) return hipErrorInvalidValue;
+  const int nb = (int)arc_index_tiles(m);
+  k_arc_compact<<<dim3(nb, 2), kBlock, 0, stream>>>(S, ncols, m, cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_arc_offsets<<<grid_for((int64_t)n + 1, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
-      off, n, pos, off_out);
+  k_arc_offsets<<<dim3(grid_for((int64_t)n + 1, kBlock, kMaxGridSimple), 2), kBlock, 0, stream>>>(
+      S, n);
   return hipGetLastError();
 }
 

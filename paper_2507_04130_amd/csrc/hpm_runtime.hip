@@ -159,7 +159,7 @@ struct Workspace {
   DevBuf la[kMaxK];
   // arc-predicate index: arc positions, block sums, and the restricted
   // out- and in-adjacency with their attribute columns
-  DevBuf apos, absum, aoff_out, anbrs_out, aoff_in, anbrs_in;
+  DevBuf amask, awpre, absum, aoff_out, anbrs_out, aoff_in, anbrs_in;
   DevBuf acol_out[kMaxCols], acol_in[kMaxCols];
   unsigned long long* host = nullptr;  // pinned readback slots
   DevPlan* host_plan = nullptr;        // pinned staging for the plan upload
@@ -175,7 +175,7 @@ struct Workspace {
                fkeys.bytes + frep.bytes + fdense.bytes + fslot_key.bytes + fslot_rep.bytes +
                fslot_region.bytes + fcount.bytes + fpbase.bytes + fpbsum.bytes + fpcnt.bytes +
                fpslot.bytes + fpdesc.bytes + ftmp.bytes + crest.bytes + cbsum.bytes +
-               apos.bytes + absum.bytes + aoff_out.bytes + anbrs_out.bytes + aoff_in.bytes +
+               amask.bytes + awpre.bytes + absum.bytes + aoff_out.bytes + anbrs_out.bytes + aoff_in.bytes +
                anbrs_in.bytes;
     for (int c = 0; c < kMaxCols; ++c) s += acol_out[c].bytes + acol_in[c].bytes;
     for (int d = 0; d < kMaxK; ++d)
@@ -193,7 +193,7 @@ struct Workspace {
     fpbase.release(); fpbsum.release(); fpcnt.release(); fpslot.release(); fpdesc.release();
     ftmp.release();
     crest.release(); cbsum.release();
-    apos.release(); absum.release(); aoff_out.release(); anbrs_out.release();
+    amask.release(); awpre.release(); absum.release(); aoff_out.release(); anbrs_out.release();
     aoff_in.release(); anbrs_in.release();
     for (int c = 0; c < kMaxCols; ++c) {
       acol_out[c].release();
@@ -1077,7 +1077,7 @@ struct Matcher {
   void build_arc_index(uint32_t flags) {
     if (host_plan.mode != HPM_MONO || k < 3 || (flags & HPM_F_NO_ARC_INDEX)) return;
     const int32_t nc = G->n_ecols;
-    if (nc == 0) return;
+    if (nc == 0 || G->m == 0) return;
     int32_t lo[kMaxCols], hi[kMaxCols];
     for (int c = 0; c < kMaxCols; ++c) {
       lo[c] = INT32_MAX;
@@ -1103,58 +1103,50 @@ struct Matcher {
       if ((cmask >> c) & 1u) frac = std::min(frac, sample_fraction(G->esample[c], lo[c], hi[c]));
     if (frac > 0.75) return;
     const int64_t m = G->m;
-    const int64_t nb = (m + 1 + 4095) / 4096;
-    const uint64_t fixed = (uint64_t)(m + 1) * 4 + (uint64_t)(nb + 2) * 8 +
-                           2 * (uint64_t)(G->n + 1) * 4;
-    if (planned + extra(W->apos, (size_t)(m + 1) * 4) > budget ||
-        planned + fixed > budget)
-      return;
-    need(W->apos, (size_t)(m + 1) * 4);
-    need(W->absum, (size_t)(nb + 2) * 8);
-    int32_t* pos = W->apos.as<int32_t>();
-    const int32_t* cols_out[kMaxCols] = {};
-    const int32_t* cols_in[kMaxCols] = {};
-    for (int c = 0; c < kMaxCols; ++c) {
-      cols_out[c] = G->ecols[c].as<int32_t>();
-      cols_in[c] = G->ecols_in[c].as<int32_t>();
+    const int64_t nb = hpm::arc_index_tiles(m);
+    const uint64_t words = (uint64_t)hpm::arc_index_words(m);
+    const uint64_t fixed = 2 * words * 12 + 2 * (uint64_t)(nb + 1) * 8 + 16;
+    if (planned + fixed > budget) return;
+    need(W->amask, (size_t)(2 * words * 8));
+    need(W->awpre, (size_t)(2 * words * 4));
+    need(W->absum, (size_t)(2 * (nb + 1) * 8 + 16));
+    hpm::ArcIndexSides S{};
+    for (int side = 0; side < 2; ++side) {
+      hpm::ArcIndexSide& sd = S.s[side];
+      sd.off = side ? G->in_off.as<int32_t>() : G->out_off.as<int32_t>();
+      sd.nbrs = side ? G->in_nbrs.as<int32_t>() : G->out_nbrs.as<int32_t>();
+      for (int c = 0; c < kMaxCols; ++c)
+        sd.cols[c] = side ? G->ecols_in[c].as<int32_t>() : G->ecols[c].as<int32_t>();
+      sd.mask = W->amask.as<uint64_t>() + side * words;
+      sd.wpre = W->awpre.as<int32_t>() + side * words;
+      sd.bsum = W->absum.as<int64_t>() + side * (nb + 1);
     }
-    // out side: positions, the number of passing arcs, then the arrays
+    int64_t* totals = W->absum.as<int64_t>() + 2 * (nb + 1);
     launch(HPM_K_INDEX, [&] {
-      return hpm::launch_arc_index_flags(cols_out, lo, hi, cmask, m, pos,
-                                         W->absum.as<int64_t>(), stream);
+      return hpm::launch_arc_index_count(S, lo, hi, cmask, m, totals, stream);
     });
-    const int64_t mp = (int64_t)read_i32(pos + m);
+    int64_t tot[2];
+    read_i64s(totals, 2, tot);
+    const int64_t mp = tot[0];
+    if (mp < 0 || mp > m || tot[1] != mp) fail(HPM_E_INTERNAL, "arc index count out of range");
     const uint64_t arrays = 2 * ((uint64_t)(G->n + 1) * 4 + (uint64_t)mp * 4 * (1 + nc));
-    if (mp < 0 || mp > m) fail(HPM_E_INTERNAL, "arc index count out of range");
     if (planned + arrays > budget) return;
     need(W->aoff_out, (size_t)(G->n + 1) * 4);
     need(W->anbrs_out, (size_t)std::max<int64_t>(mp, 1) * 4);
     need(W->aoff_in, (size_t)(G->n + 1) * 4);
     need(W->anbrs_in, (size_t)std::max<int64_t>(mp, 1) * 4);
-    int32_t* co[kMaxCols] = {};
-    int32_t* ci[kMaxCols] = {};
     for (int32_t c = 0; c < nc; ++c) {
       need(W->acol_out[c], (size_t)std::max<int64_t>(mp, 1) * 4);
       need(W->acol_in[c], (size_t)std::max<int64_t>(mp, 1) * 4);
-      co[c] = W->acol_out[c].as<int32_t>();
-      ci[c] = W->acol_in[c].as<int32_t>();
+      S.s[0].cols_out[c] = W->acol_out[c].as<int32_t>();
+      S.s[1].cols_out[c] = W->acol_in[c].as<int32_t>();
     }
+    S.s[0].off_out = W->aoff_out.as<int32_t>();
+    S.s[0].nbrs_out = W->anbrs_out.as<int32_t>();
+    S.s[1].off_out = W->aoff_in.as<int32_t>();
+    S.s[1].nbrs_out = W->anbrs_in.as<int32_t>();
     launch(HPM_K_INDEX, [&] {
-      return hpm::launch_arc_index_fill(G->out_off.as<int32_t>(), G->n,
-                                        G->out_nbrs.as<int32_t>(), cols_out, nc, lo, hi, cmask, m,
-                                        pos, W->aoff_out.as<int32_t>(),
-                                        W->anbrs_out.as<int32_t>(), co, stream);
-    });
-    // in side (the transpose: the same arcs pass)
-    launch(HPM_K_INDEX, [&] {
-      return hpm::launch_arc_index_flags(cols_in, lo, hi, cmask, m, pos,
-                                         W->absum.as<int64_t>(), stream);
-    });
-    launch(HPM_K_INDEX, [&] {
-      return hpm::launch_arc_index_fill(G->in_off.as<int32_t>(), G->n, G->in_nbrs.as<int32_t>(),
-                                        cols_in, nc, lo, hi, cmask, m, pos,
-                                        W->aoff_in.as<int32_t>(), W->anbrs_in.as<int32_t>(), ci,
-                                        stream);
+      return hpm::launch_arc_index_fill(S, G->n, nc, m, mp, stream);
     });
     g.m = (int32_t)mp;
     g.out_off = W->aoff_out.as<int32_t>();
@@ -1169,12 +1161,12 @@ struct Matcher {
     indexed = true;
   }
 
-  int32_t read_i32(const int32_t* p) {
-    hip_check(hipMemcpyAsync(W->host + kCntSlots, p, sizeof(int32_t), hipMemcpyDeviceToHost,
-                             stream),
+  void read_i64s(const int64_t* p, int count, int64_t* out) {
+    hip_check(hipMemcpyAsync(W->host + kCntSlots, p, sizeof(int64_t) * count,
+                             hipMemcpyDeviceToHost, stream),
               "readback");
     sync();
-    return *reinterpret_cast<const int32_t*>(W->host + kCntSlots);
+    for (int i = 0; i < count; ++i) out[i] = (int64_t)W->host[kCntSlots + i];
   }
 
   void run() {
@@ -1243,12 +1235,16 @@ struct Matcher {
         if ((double)s2 * (double)m / (double)(e1 - e0) >= (double)m / 256.0) {
           build_arc_index(call_flags);
           if (indexed) {
-            // degrees counted over the index only: a stronger validator for
-            // the later positions (and for the scan of later arc chunks)
+            // degrees counted over the index only: a stronger validator, so
+            // the chunk is scanned again with it (one more pass over its arcs
+            // for a frontier that is often much smaller)
             launch(HPM_K_VERTEX_VALIDATOR, [&] {
               return hpm::launch_vertex_validator(g, dplan(), W->vbits.as<uint32_t>(),
                                                   bit_words(), stream);
             });
+            st.survivors -= (uint64_t)s2;
+            e0 -= cap2;  // the loop's step returns to this chunk
+            continue;
           }
         }
       }
@@ -1302,6 +1298,8 @@ struct SurvivorsOut {
 };
 
 constexpr uint64_t kMinChunkRows = hpm::kExpandTile;
+// Frontier rows a deeper chunk keeps before the depth-2 chunk takes the rest.
+constexpr uint64_t kDeepFloorRows = uint64_t(1) << 22;
 // Piece sizes of a first-k search (arcs per scan chunk, work items per
 // frontier chunk).
 constexpr int64_t kFirstKArcs = int64_t(1) << 20;
@@ -1547,8 +1545,12 @@ int match_one(hpm_graph* G, const hpm_pattern* p, int mode, hipStream_t stream, 
       for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += row_bytes(d);
       const uint64_t m_round =
           ((uint64_t)G->m + hpm::kScanTile - 1) / hpm::kScanTile * hpm::kScanTile;
+      // Depth-2 rows take all arcs in one chunk when what is left still holds
+      // kDeepFloorRows frontier rows; a smaller budget is split in halves.
+      const uint64_t deep_floor =
+          per_row_deep ? std::min<uint64_t>(avail / 2, per_row_deep * kDeepFloorRows) : 0;
       uint64_t c2 = std::min<uint64_t>(std::max<uint64_t>(m_round, hpm::kScanTile),
-                                       (per_row_deep ? avail / 2 : avail) / kDepth2BytesPerArc);
+                                       (avail - deep_floor) / kDepth2BytesPerArc);
       c2 = c2 / hpm::kScanTile * hpm::kScanTile;
       c2 = std::min<uint64_t>(c2, (uint64_t)INT32_MAX / hpm::kScanTile * hpm::kScanTile);
       if (c2 < (uint64_t)hpm::kScanTile) fail(HPM_E_NOMEM, "scratch budget below one arc chunk");
