@@ -1682,7 +1682,14 @@ uint64_t estimate_scratch(const hpm_graph* G, const DevPlan& pl) {
                 (pl.mve_forward ? arc_fraction(G, pl, 0, 1) : arc_fraction(G, pl, 1, 0));
   if (pl.rev_rule == 1) rows *= arc_fraction(G, pl, 1, 0) * std::min(1.0, deg / n);
   double bytes = (double)scratch_fixed(G, k);
-  if (k >= 3) bytes += (double)kDepth2BytesPerArc * (double)G->m;
+  // one depth-2 chunk of every arc (rounded to scan tiles) and the frontier
+  // floor the planner keeps beside it, so a budget of this size scans in one
+  // chunk
+  if (k >= 3)
+    bytes += (double)kDepth2BytesPerArc * ((double)G->m + hpm::kScanTile);
+  double per_row_deep = 0.0;
+  for (int32_t d = 3; d <= k - 1; ++d) per_row_deep += (double)row_bytes(d);
+  bytes += per_row_deep * (double)kDeepFloorRows;
   for (int32_t d = 2; d + 1 < k; ++d) {
     double f = deg * vertex_fraction(G, pl, d);
     int arcs = 0;
@@ -1745,6 +1752,9 @@ struct hpm_server {
   bool stop = false;
   std::string start_error;
   std::vector<std::thread> threads;
+  // workspaces of queries not running, most recently returned last; a query
+  // takes the warmest (allocations already grown to the pool's sizes)
+  std::vector<std::unique_ptr<Workspace>> spare;
   // Dispatch without a wake-up: while the server has idle workers, one of them
   // (the spinner) polls `events` instead of sleeping on cv_work, so a query
   // that arrives at an idle server starts within microseconds; the others
@@ -1771,11 +1781,11 @@ struct hpm_server {
   void worker() {
     using clock = std::chrono::steady_clock;
     hipStream_t s = nullptr;
-    std::unique_ptr<Workspace> W(new Workspace());
     const bool ok = hipSetDevice(G->device) == hipSuccess &&
                     hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     for (;;) {
       std::unique_ptr<Query> q;
+      std::unique_ptr<Workspace> W;
       bool spin = false;
       uint64_t seen = 0;
       {
@@ -1792,7 +1802,9 @@ struct hpm_server {
         });
         if (!q && !spin) break;  // stopping with an empty queue
         if (q) {
-          // admitted: its grant is taken under the same lock that picked it
+          // admitted: its grant is taken under the same lock that picked it,
+          // and the workspace returned last (the warmest) comes with it
+          W = take_workspace();
           in_use += q->grant;
           peak_in_use = std::max(peak_in_use, in_use);
           running++;
@@ -1837,6 +1849,7 @@ struct hpm_server {
       const auto t1 = clock::now();
       {
         std::lock_guard<std::mutex> lk(mu);
+        spare.push_back(std::move(W));
         in_use -= q->grant;
         running--;
         events.fetch_add(1, std::memory_order_release);
@@ -1854,8 +1867,21 @@ struct hpm_server {
       cv_done.notify_all();
       cv_work.notify_all();
     }
-    W.reset();
     if (s) (void)hipStreamDestroy(s);
+  }
+
+  // A workspace for an admitted query (caller holds mu): the one returned
+  // last, else a new one.  At most `workers` exist.
+  std::unique_ptr<Workspace> take_workspace() {
+    if (spare.empty()) return std::unique_ptr<Workspace>(new Workspace());
+    std::unique_ptr<Workspace> W = std::move(spare.back());
+    spare.pop_back();
+    return W;
+  }
+
+  ~hpm_server() {
+    if (G) (void)hipSetDevice(G->device);  // the workspaces free device memory
+    spare.clear();
   }
 };
 
