@@ -1476,20 +1476,70 @@ __global__ __launch_bounds__(kBlock) void k_filter_pieces(DevGraph g,
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// One block per piece of a group (pbase: the exclusive prefix sums of the
-// pieces per group, pbase[nslots] their total; blocks at or past the total
-// exit): order-preserving compaction of the candidates of the piece's part of
-// the representative row's pivot list that pass the vertex validator of
-// position a, the pivot-arc predicate and every other condition between a and
-// the positions in rmask (rmask == 0: the pivot position alone).  A piece is
-// taken kExpandTile entries at a time (4 consecutive ones per thread); every
-// checked list is cut once per tile to the tile's id range, staged in LDS
-// when short enough and searched there, else searched in the cut range.  A
-// one-piece group writes its list to pool + slot_region[s] and its length to
-// fcount[s]; a piece of a longer group writes to tmp at the piece's own
-// offset in the group's region, for k_filter_merge.  Every piece leaves its
-// count in pcnt; pslot[blk] names the block's group and pdesc[blk] its list
-// range, pivot code and row (k_filter_map).
+// One wavefront per piece of a group (four per block; pbase: the exclusive
+// prefix sums of the pieces per group, pbase[nslots] their total; wavefronts
+// at or past the total exit): order-preserving compaction of the candidates of
+// the piece's part of the representative row's pivot list that pass the
+// vertex validator of position a, the pivot-arc predicate and every other
+// condition between a and the positions in rmask (rmask == 0: the pivot
+// position alone).  A piece is taken kFilterWaveTile entries at a time (entry
+// base + 64 * it + lane in item it of a lane, so loads and stores are
+// coalesced); every checked list is cut once per tile to the tile's id range,
+// staged in the wavefront's LDS slice when short enough and searched there,
+// else searched in the cut range.  Pieces are mostly short lists, so nothing
+// waits on the other wavefronts of the block.  A one-piece group writes its
+// list to pool + slot_region[s] and its length to fcount[s]; a piece of a
+// longer group writes to tmp at the piece's own offset in the group's region,
+// for k_filter_merge.  Every piece leaves its count in pcnt; pslot[piece]
+// names its group and pdesc[piece] its list range, pivot code and row
+// (k_filter_map).
+constexpr int kFilterWaveItems = 4;
+constexpr int kFilterWaveTile = 64 * kFilterWaveItems;
+
+// Membership of the lanes' candidates c[] (those with their bit in keep) in
+// the ascending run cl[lo, hi), cut to [cmin, cmax] and staged in wl when it
+// fits.  Returns the bits whose candidate passes: present (and, with need,
+// passing the arc predicate at the found position) when req, absent else.
+__device__ __forceinline__ uint32_t filter_check(const DevGraph& g, const DevPlan* __restrict__ P,
+                                                 int32_t a, int32_t q, bool in_dir, bool req,
+                                                 int32_t lo, int32_t hi, int32_t cmin,
+                                                 int32_t cmax, const int32_t (&c)[kFilterWaveItems],
+                                                 uint32_t keep, int32_t* wl, int lane) {
+  const int32_t* __restrict__ cl = in_dir ? g.in_nbrs : g.out_nbrs;
+  if (hi - lo > kWaveList) {
+    lo = wave_bound<int32_t>(cl, lo, hi, cmin, false);
+    hi = wave_bound<int32_t>(cl, lo, hi, cmax, true);
+  }
+  const int32_t len = hi - lo;
+  const bool staged = len <= kWaveList;
+  if (staged) {
+    wave_sync();  // earlier readers of wl are done
+    for (int32_t t = lane; t < len; t += 64) wl[t] = cl[lo + t];
+    wave_sync();
+  }
+  const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
+#pragma unroll
+  for (int it = 0; it < kFilterWaveItems; ++it) {
+    if (!((keep >> it) & 1u)) continue;
+    int32_t pos;
+    if (staged) {
+      const int32_t x = lds_find(wl, len, c[it]);
+      pos = x >= 0 ? lo + x : -1;
+    } else {
+      pos = find_in(cl, lo, hi, c[it]);
+    }
+    bool ok;
+    if (!req)
+      ok = pos < 0;
+    else if (!need)
+      ok = pos >= 0;
+    else
+      ok = pos >= 0 && (in_dir ? arc_ok_in(g, P, a, q, pos) : arc_ok(g, P, q, a, pos));
+    if (!ok) keep &= ~(1u << it);
+  }
+  return keep;
+}
+
 __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPlan* __restrict__ P,
                                                          const uint32_t* __restrict__ abits,
                                                          int32_t a, const int32_t* __restrict__ rows,
@@ -1503,147 +1553,85 @@ __global__ __launch_bounds__(kBlock) void k_filter_lists(DevGraph g, const DevPl
                                                          int32_t* __restrict__ pcnt,
                                                          const int32_t* __restrict__ pslot,
                                                          const int4* __restrict__ pdesc) {
-  __shared__ int32_t s_scan[kWaves + 1];
-  __shared__ int32_t s_f[kMaxK];
-  __shared__ int32_t s_cons[kMaxCons], s_wlo[kMaxCons], s_whi[kMaxCons], s_woff[kMaxCons];
+  __shared__ int32_t s_f[kWaves][kMaxK];
   __shared__ int32_t s_pool[kTilePool];
-  __shared__ int32_t s_n;
-  const int64_t blk = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t piece = (int64_t)blockIdx.x * kWaves + wave;
   // the group, its list range, pivot code and row (or pivot vertex) are read
   // beside the total and used only below it
   const int64_t total = pbase[nslots];
-  const int32_t s = pslot[blk];
-  const int4 pd = pdesc[blk];
-  if (blk >= total) return;
+  if (piece >= total) return;  // the whole wavefront: no block barrier follows
+  const int32_t s = pslot[piece];
+  const int4 pd = pdesc[piece];
   const int32_t d = a;
   const int32_t code = pd.z;
   const int64_t i = rmask ? pd.w : 0;
-  const int32_t pv_v = rmask ? 0 : pd.w;
   const int32_t b = code >> 2;
   const bool out_dir = (code & 1) != 0;
   const uint32_t fw = P->fwd[a], bw = P->bwd[a];
   const bool iso = P->mode == 0;
-  const int lane = threadIdx.x & 63;
-  if (rmask && threadIdx.x < d) s_f[threadIdx.x] = rows[i * d + threadIdx.x];
-  if (!rmask && threadIdx.x == 0) s_f[b] = pv_v;
+  int32_t* f = s_f[wave];
+  int32_t* wl = s_pool + wave * kWaveList;
+  if (rmask) {
+    if (lane < d) f[lane] = rows[i * d + lane];
+  } else if (lane == 0) {
+    f[b] = pd.w;
+  }
+  wave_sync();
   // relations checked here: every condition with a position in rmask (with
   // the pivot position alone for pivot-list groups) but the pivot arc itself
   const uint32_t cmask = rmask ? rmask : (1u << b);
-  if (threadIdx.x == 0) {
-    int32_t n = 0;
-    for (int q = 0; q < d; ++q) {
-      if (!((cmask >> q) & 1u)) continue;
-      const bool arc_in = (fw >> q) & 1u, arc_out = (bw >> q) & 1u;
-      if (arc_in ? !(q == b && out_dir) : iso) s_cons[n++] = pack_cons(q, 0, arc_in);
-      if (arc_out ? !(q == b && !out_dir) : iso) s_cons[n++] = pack_cons(q, 1, arc_out);
-    }
-    s_n = n;
-  }
-  __syncthreads();
-  const int32_t ncons = s_n;
   const int32_t lo = pd.x, hi = pd.y;
-  const int32_t* lst = out_dir ? g.out_nbrs : g.in_nbrs;
+  const int32_t* __restrict__ lst = out_dir ? g.out_nbrs : g.in_nbrs;
   const int64_t p0 = pbase[s];
   const int64_t npieces = pbase[s + 1] - p0;
-  int32_t* dst = npieces == 1 ? pool + slot_region[s] : tmp + slot_region[s] + (blk - p0) * plen;
+  int32_t* dst = npieces == 1 ? pool + slot_region[s] : tmp + slot_region[s] + (piece - p0) * plen;
   int32_t run = 0;
-  for (int32_t base = lo; base < hi; base += kExpandTile) {
-    const int32_t end = base + kExpandTile < hi ? base + kExpandTile : hi;
-    int32_t c[kExpandItems];
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int32_t base = lo; base < hi; base += kFilterWaveTile) {
+    const int32_t end = base + kFilterWaveTile < hi ? base + kFilterWaveTile : hi;
+    int32_t c[kFilterWaveItems];
     uint32_t keep = 0;
 #pragma unroll
-    for (int it = 0; it < kExpandItems; ++it) {
-      const int32_t x = base + (int32_t)threadIdx.x * kExpandItems + it;
-      c[it] = 0;
+    for (int it = 0; it < kFilterWaveItems; ++it) {
+      const int32_t x = base + 64 * it + lane;
+      c[it] = x < end ? lst[x] : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < kFilterWaveItems; ++it) {
+      const int32_t x = base + 64 * it + lane;
       if (x < end) {
-        const int32_t cc = lst[x];
-        c[it] = cc;
+        const int32_t cc = c[it];
         bool ok = ((abits[cc >> 5] >> (cc & 31)) & 1u) != 0;
         if (ok) ok = out_dir ? arc_ok(g, P, b, a, x) : arc_ok_in(g, P, a, b, x);
         keep |= (uint32_t)ok << it;
       }
     }
-    if (ncons > 0) {
-      const int32_t cmin = lst[base], cmax = lst[end - 1];
-      // cut every checked list to [cmin, cmax]; stage what fits
-      for (int32_t ci = threadIdx.x >> 6; ci < ncons; ci += kWaves) {
-        const int32_t desc = s_cons[ci];
-        const int32_t fq = s_f[desc & 31];
-        const bool in_dir = ((desc >> 5) & 1) != 0;
-        const int32_t* cl = in_dir ? g.in_nbrs : g.out_nbrs;
-        const int32_t l = in_dir ? g.in_off[fq] : g.out_off[fq];
-        const int32_t h = in_dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
-        const int32_t wlo = wave_bound<int32_t>(cl, l, h, cmin, false);
-        const int32_t whi = wave_bound<int32_t>(cl, wlo, h, cmax, true);
-        if (lane == 0) {
-          s_wlo[ci] = wlo;
-          s_whi[ci] = whi;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int32_t acc = 0;
-        for (int32_t ci = 0; ci < ncons; ++ci) {
-          const int32_t len = s_whi[ci] - s_wlo[ci];
-          if (acc + len <= kTilePool) {
-            s_woff[ci] = acc;
-            acc += len;
-          } else {
-            s_woff[ci] = -1;
-          }
-        }
-      }
-      __syncthreads();
-      for (int32_t ci = 0; ci < ncons; ++ci) {
-        const int32_t woff = s_woff[ci];
-        if (woff < 0) continue;
-        const int32_t* cl = ((s_cons[ci] >> 5) & 1) ? g.in_nbrs : g.out_nbrs;
-        const int32_t wlo = s_wlo[ci], len = s_whi[ci] - wlo;
-        for (int32_t x = threadIdx.x; x < len; x += kBlock) s_pool[woff + x] = cl[wlo + x];
-      }
-      __syncthreads();
-      for (int32_t ci = 0; ci < ncons; ++ci) {
-        const int32_t desc = s_cons[ci];
-        const int q = desc & 31;
-        const bool in_dir = ((desc >> 5) & 1) != 0;
-        const bool req = ((desc >> 6) & 1) != 0;
-        const int32_t* cl = in_dir ? g.in_nbrs : g.out_nbrs;
-        const int32_t wlo = s_wlo[ci], whi = s_whi[ci], woff = s_woff[ci];
-        const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
-#pragma unroll
-        for (int it = 0; it < kExpandItems; ++it) {
-          if (!((keep >> it) & 1u)) continue;
-          int32_t pos;
-          if (woff >= 0) {
-            const int32_t x = lds_find(s_pool + woff, whi - wlo, c[it]);
-            pos = x >= 0 ? wlo + x : -1;
-          } else {
-            pos = find_in(cl, wlo, whi, c[it]);
-          }
-          bool ok;
-          if (!req)
-            ok = pos < 0;
-          else if (!need)
-            ok = pos >= 0;
-          else
-            ok = pos >= 0 && (in_dir ? arc_ok_in(g, P, a, q, pos) : arc_ok(g, P, q, a, pos));
-          if (!ok) keep &= ~(1u << it);
-        }
-      }
+    const int32_t cmin = lst[base], cmax = lst[end - 1];
+    for (int q = 0; q < d; ++q) {
+      if (!((cmask >> q) & 1u)) continue;
+      if (!__any(keep != 0)) break;  // wave-uniform
+      const int32_t fq = f[q];
+      const bool arc_in = (fw >> q) & 1u;   // pattern arc q -> a: f(q) -> c in out(f(q))
+      const bool arc_out = (bw >> q) & 1u;  // pattern arc a -> q: c -> f(q) in in(f(q))
+      if (arc_in ? !(q == b && out_dir) : iso)
+        keep = filter_check(g, P, a, q, false, arc_in, g.out_off[fq], g.out_off[fq + 1], cmin,
+                            cmax, c, keep, wl, lane);
+      if (arc_out ? !(q == b && !out_dir) : iso)
+        keep = filter_check(g, P, a, q, true, arc_out, g.in_off[fq], g.in_off[fq + 1], cmin,
+                            cmax, c, keep, wl, lane);
     }
-    // list order is thread order, then item order: one scan of per-thread counts
-    int32_t tot;
-    const int32_t ex = block_exclusive_scan<int32_t>(__popc(keep), s_scan, &tot);
-    int32_t o = run + ex;
+    // list order is item order, then lane order
 #pragma unroll
-    for (int it = 0; it < kExpandItems; ++it)
-      if ((keep >> it) & 1u) dst[o++] = c[it];
-    run += tot;
-    __syncthreads();  // s_wlo / s_pool are rewritten by the next tile
+    for (int it = 0; it < kFilterWaveItems; ++it) {
+      const uint64_t m = __ballot((keep >> it) & 1u);
+      if ((keep >> it) & 1u) dst[run + __popcll(m & below)] = c[it];
+      run += __popcll(m);
+    }
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     if (npieces == 1) fcount[s] = run;
-    pcnt[blk] = run;
+    pcnt[piece] = run;
   }
 }
 
@@ -2260,8 +2248,10 @@ hipError_t launch_filter_lists(const DevGraph& g, const DevPlan* plan, const uin
                                int32_t* tmp, int32_t* pcnt, const int32_t* pslot,
                                const int4* pdesc, hipStream_t stream) {
   if (nslots <= 0 || grid <= 0) return hipSuccess;
-  k_filter_lists<<<grid, kBlock, 0, stream>>>(g, plan, abits, a, rows, rmask, nslots, pbase, plen,
-                                              slot_region, pool, fcount, tmp, pcnt, pslot, pdesc);
+  // one wavefront per piece
+  k_filter_lists<<<(grid + kWaves - 1) / kWaves, kBlock, 0, stream>>>(
+      g, plan, abits, a, rows, rmask, nslots, pbase, plen, slot_region, pool, fcount, tmp, pcnt,
+      pslot, pdesc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tmp == nullptr) return e;
   k_filter_merge<<<(grid + kMergePieces - 1) / kMergePieces, kBlock, 0, stream>>>(
