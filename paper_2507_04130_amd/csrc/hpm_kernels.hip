@@ -689,7 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   //  * wavefront inside one row: checked lists of at most kWaveList entries
   //    are staged in the wavefront's LDS slice;
   //  * otherwise each lane binary-searches the list of the mapped vertex.
-  __shared__ int64_t s_off[kExpandTile + 1];
+  // s_off: the tile's row offsets relative to its first item (clamped; the
+  // first row's true offset is off[r_lo])
+  __shared__ int32_t s_off[kExpandTile + 2];
   __shared__ int2 s_piv[kExpandTile];
   __shared__ int32_t s_rows[kLdsRowInts];
   __shared__ int32_t s_pool[kTilePool];
@@ -741,7 +743,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(
     const bool rows_lds = use_lds && nrow * d <= kLdsRowInts;
     if (use_lds) {
       if (!LONG)
-        for (int32_t i = threadIdx.x; i <= nrow; i += kBlock) s_off[i] = off[r_lo + i];
+        for (int32_t i = threadIdx.x; i <= nrow; i += kBlock) {
+          const int64_t rel = off[r_lo + i] - tb;
+          s_off[i] = (int32_t)(rel < -1 ? -1 : (rel > kExpandTile + 1 ? kExpandTile + 1 : rel));
+        }
       for (int32_t i = threadIdx.x; i < nrow; i += kBlock) s_piv[i] = piv[r_lo + i];
       if (rows_lds)
         for (int32_t i = threadIdx.x; i < nrow * d; i += kBlock)
@@ -813,17 +818,18 @@ __global__ __launch_bounds__(kBlock) void k_expand(
           j = w;
           pv = s_piv[0];
         } else if (use_lds) {
+          const int32_t wr = (int32_t)(w - tb);
           int32_t lo = 0, hi = nrow - 1;
           while (lo < hi) {
             const int32_t mid = lo + ((hi - lo + 1) >> 1);
-            if (s_off[mid] <= w)
+            if (s_off[mid] <= wr)
               lo = mid;
             else
               hi = mid - 1;
           }
           li = lo;
           i = r_lo + lo;
-          j = w - s_off[lo];
+          j = lo ? (int64_t)(wr - s_off[lo]) : w - off[r_lo];
           pv = s_piv[lo];
         } else {
           int32_t lo = r_lo, hi = r_hi;

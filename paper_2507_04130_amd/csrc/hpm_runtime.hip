@@ -1007,18 +1007,23 @@ struct Matcher {
       return;
     }
     int64_t S = work, T = 0;
-    if (work <= chunk && split_rows(d, r, offp, work, &S, &T)) {
-      // the whole depth in one piece: packed short rows and row-aligned long rows
+    if (split_rows(d, r, offp, work, &S, &T)) {
+      // The whole depth in one piece: packed short rows and row-aligned long
+      // rows.  Room for at most one frontier chunk of new rows: with more
+      // candidates than that, the piece is tried first (most candidates
+      // fail), and only if more rows pass than fit is the depth redone in
+      // chunks of candidates below.
+      const int64_t cap_rows = std::min(work, chunk);
       st.chunks++;
-      need(W->rows[d + 1], (size_t)work * (d + 1) * sizeof(int32_t));
-      ensure_depth(d + 1, work);
+      need(W->rows[d + 1], (size_t)cap_rows * (d + 1) * sizeof(int32_t));
+      ensure_depth(d + 1, cap_rows);
       int32_t* out = W->rows[d + 1].as<int32_t>();
       zero_counter(kCntCursor);
       if (S > 0)
         launch(HPM_K_EXPAND, [&] {
           return hpm::launch_expand(g, dplan(), bits(d), d, rows, W->soff[d].as<int64_t>(), piv,
                                     fpool, (int32_t)r, 0, S, nullptr, done[d], 0, out,
-                                    counters() + kCntCursor, (unsigned long long)work,
+                                    counters() + kCntCursor, (unsigned long long)cap_rows,
                                     W->partials.as<unsigned long long>(),
                                     grid_for(S, hpm::kExpandTile), stream);
         });
@@ -1026,14 +1031,18 @@ struct Matcher {
         return hpm::launch_expand(g, dplan(), bits(d), d, rows, offp, piv, fpool, (int32_t)r, 0,
                                   T, W->toff[d].as<int64_t>(), done[d], 0, out,
                                   counters() + kCntCursor,
-                                  (unsigned long long)work, W->partials.as<unsigned long long>(),
+                                  (unsigned long long)cap_rows,
+                                  W->partials.as<unsigned long long>(),
                                   grid_for(T * hpm::kExpandTile, hpm::kExpandTile), stream);
       });
       const int64_t r1 = (int64_t)read_counter(kCntCursor);
       if (r1 > work) fail(HPM_E_INTERNAL, "frontier overflow");
-      process_depth(d + 1, out, r1);
-      check_limit();
-      return;
+      if (r1 <= cap_rows) {
+        process_depth(d + 1, out, r1);
+        check_limit();
+        return;
+      }
+      // rows were dropped: the chunked pass below
     }
     for (int64_t w0 = 0; w0 < work && !stopped; w0 += chunk) {
       const int64_t w1 = std::min(work, w0 + chunk);
