@@ -385,11 +385,15 @@ int hpm_last_batch_stats(hpm_batch_stats* out);
  * run as soon as a worker is free and the query is admitted: each query's
  * scratch need is estimated on submission from the pattern and host-side
  * statistics of the graph (attribute-column samples, size-biased mean degree),
- * and it is granted that many bytes (at least min(256 MiB, budget / 2), at
- * most budget / 2) out of a pool of budget / 2; the query then runs exactly as
+ * and it is granted twice that many bytes (at least min(256 MiB, budget / 2),
+ * at most budget / 2; the estimate of deep frontiers is rough, and a query
+ * granted less than its frontiers need runs in more pieces) out of a pool of
+ * budget / 2; the query then runs exactly as
  * hpm_match with the grant as its scratch limit, so its result does not depend
- * on the grant or on the other queries in flight.  Each worker keeps at most
- * budget / (2 workers) of allocations between queries, so device scratch
+ * on the grant or on the other queries in flight.  Workspaces (device
+ * allocations reused between queries) are shared by the workers, a query
+ * taking the one returned last; those not in use keep at most budget / 2 in
+ * all (the least recently used give theirs back first), so device scratch
  * stays within the budget.  Admission is in arrival order, except that a query
  * that does not fit may be overtaken by later ones that do, at most 32 times.
  * Queries submitted while others run join them on the device (continuous

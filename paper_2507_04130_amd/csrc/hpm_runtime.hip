@@ -1723,9 +1723,9 @@ uint64_t estimate_scratch(const hpm_graph* G, const DevPlan& pl) {
 // Queries are admitted in arrival order by their estimated scratch bytes
 // against a fixed budget: half of it is lent out as per-query grants (each
 // query runs with its grant as its scratch limit, so the chunked expansion
-// keeps it inside), and each worker may keep up to budget / (2 workers) of
-// allocations between queries; device scratch therefore never exceeds the
-// budget.  A query that does not fit waits while later ones that fit go
+// keeps it inside), and the workspaces of queries not running keep at most
+// the other half between queries (the least recently used give theirs back
+// first); device scratch therefore stays within the budget.  A query that does not fit waits while later ones that fit go
 // ahead, at most kMaxBypass times, after which it blocks the queue until it
 // fits.
 struct hpm_server {
@@ -1851,14 +1851,19 @@ struct hpm_server {
         status = HPM_E_INTERNAL;
         err = "unknown internal error";
       }
-      if (W->held() > keep) {
-        if (s) (void)hipStreamSynchronize(s);
-        W->release_all();
-      }
+      if (s) (void)hipStreamSynchronize(s);  // nothing of this query is left in flight
       const auto t1 = clock::now();
       {
         std::lock_guard<std::mutex> lk(mu);
         spare.push_back(std::move(W));
+        // Cached workspaces stay within half the budget: the least recently
+        // returned give their memory back first, the warm ones are kept.
+        uint64_t held = 0;
+        for (const auto& x : spare) held += x->held();
+        for (size_t j = 0; j < spare.size() && held > keep; ++j) {
+          held -= spare[j]->held();
+          spare[j]->release_all();
+        }
         in_use -= q->grant;
         running--;
         events.fetch_add(1, std::memory_order_release);
@@ -2494,7 +2499,7 @@ int hpm_server_create(hpm_server** out, const hpm_graph* gc, const hpm_server_op
     S->flags = opts ? (opts->flags & ~(uint32_t)HPM_F_TIMING) : 0;
     S->budget = budget;
     S->grant_pool = budget / 2;
-    S->keep = budget / 2 / (uint64_t)workers;
+    S->keep = budget / 2;
     S->min_grant = std::min<uint64_t>(S->grant_pool, (uint64_t)256 << 20);
     if (S->grant_pool < scratch_fixed(G, HPM_MAX_K) + (uint64_t)hpm::kScanTile * 64)
       fail(HPM_E_NOMEM, "serving budget too small");
@@ -2537,7 +2542,9 @@ int hpm_server_submit(hpm_server* S, const hpm_pattern* p, hpm_mode mode, int32_
     const DevPlan plan = build_dev_plan(&q->p, info, plan_order(info, S->flags), G->n_vcols,
                                         G->n_ecols, (int)mode);
     q->est = estimate_scratch(G, plan);
-    q->grant = std::max(S->min_grant, std::min(q->est, S->grant_pool));
+    // twice the estimate: its deep-frontier part comes from column samples,
+    // and a query granted less than its frontiers need runs in more pieces
+    q->grant = std::max(S->min_grant, std::min(2 * q->est, S->grant_pool));
     q->t_submit = std::chrono::steady_clock::now();
     {
       std::lock_guard<std::mutex> lk(S->mu);
