@@ -281,11 +281,12 @@ hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64
 // that mask, which must contain every position tied to the new one by a
 // pattern arc (so equal keys give equal pivots).  Each table has H slots (a
 // power of two above the number of such rows), table t at keys + t * H; keys
-// must hold ~0 (empty) on entry.  distinct[t] += keys of table t.
+// must hold ~0 (empty) on entry.  Only the tables whose bit is set in
+// `tables` are filled; distinct[t] += keys of table t.
 hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
                                 const int64_t* off, int32_t min_len, uint32_t mask1,
-                                uint32_t mask2, unsigned long long* keys, uint32_t H,
-                                unsigned long long* distinct, hipStream_t stream);
+                                uint32_t mask2, uint32_t tables, unsigned long long* keys,
+                                uint32_t H, unsigned long long* distinct, hipStream_t stream);
 // Number the groups of one table (keys[H]; rmask 0 for table 0, else the
 // table-1 mask with rep[H] holding INT32_MAX on entry): dense[H] maps slots to
 // groups, slot_key (table 0) or slot_rep (table 1, the group's smallest row)

@@ -1309,13 +1309,14 @@ __device__ __forceinline__ uint32_t table_find(const unsigned long long* __restr
 // off: exclusive prefix sums of the rows' list lengths (off[r] = total).
 // Table 0 (keys[0..H)) groups by pivot list; table t = 1, 2 (keys[t*H ..)),
 // when masks[t-1] != 0, groups by the images of the positions in that mask.
-// distinct[t] counts the keys of table t.
+// Only the tables with their bit in `tables` are filled; distinct[t] counts
+// the keys of table t.
 __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restrict__ rows,
                                                           int32_t r, int32_t d,
                                                           const int2* __restrict__ piv,
                                                           const int64_t* __restrict__ off,
                                                           int32_t min_len, uint32_t mask1,
-                                                          uint32_t mask2,
+                                                          uint32_t mask2, uint32_t tables,
                                                           unsigned long long* __restrict__ keys,
                                                           uint32_t H,
                                                           unsigned long long* __restrict__ distinct) {
@@ -1325,7 +1326,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restr
     const bool ins = i < r && off[i + 1] - off[i] >= min_len;
     for (int t = 0; t < 3; ++t) {
       const uint32_t m = t == 0 ? 0u : (t == 1 ? mask1 : mask2);
-      if (t > 0 && m == 0) continue;  // uniform
+      if (!((tables >> t) & 1u) || (t > 0 && m == 0)) continue;  // uniform
       bool fresh = false;
       const unsigned long long key = ins ? row_key(rows, i, d, piv[i].x, m) : kEmptyKey;
       // neighbouring rows often share a key: the lane before inserts it
@@ -2202,11 +2203,11 @@ hipError_t launch_split_rows(const int64_t* off, int32_t r, int64_t* soff, int64
 
 hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const int2* piv,
                                 const int64_t* off, int32_t min_len, uint32_t mask1,
-                                uint32_t mask2, unsigned long long* keys, uint32_t H,
-                                unsigned long long* distinct, hipStream_t stream) {
+                                uint32_t mask2, uint32_t tables, unsigned long long* keys,
+                                uint32_t H, unsigned long long* distinct, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
   k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
-      rows, r, d, piv, off, min_len, mask1, mask2, keys, H, distinct);
+      rows, r, d, piv, off, min_len, mask1, mask2, tables, keys, H, distinct);
   return hipGetLastError();
 }
 

@@ -727,10 +727,15 @@ struct Matcher {
     unsigned long long* cnt = counters() + kCntFilterSlots;
     hip_check(hipMemsetAsync(keys, 0xff, T * H * 8, stream), "memset");
     hip_check(hipMemsetAsync(cnt, 0, 5 * sizeof(unsigned long long), stream), "memset");
-    launch(HPM_K_FILTER, [&] {
-      return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen,
-                                       masks[1], masks[2], keys, H, cnt + 2, stream);
-    });
+    // The wider keys' tables first; the pivot-list table only when neither
+    // is used (or there is none).
+    auto insert = [&](uint32_t tables) {
+      launch(HPM_K_FILTER, [&] {
+        return hpm::launch_filter_insert(rows, (int32_t)r, d, piv, off, hpm::kFilterMinLen,
+                                         masks[1], masks[2], tables, keys, H, cnt + 2, stream);
+      });
+    };
+    insert(grouped ? 6u : 1u);
     int64_t distinct[3] = {0, 0, 0};
     if (grouped) {
       hip_check(hipMemcpyAsync(W->host + kCntFilterSlots + 2, cnt + 2,
@@ -771,7 +776,10 @@ struct Matcher {
     int t_use = -1;
     for (int t = 2; t >= 1 && t_use < 0; --t)
       if (masks[t] && 2 * distinct[t] <= r && groups(t)) t_use = t;
-    if (t_use < 0 && groups(0)) t_use = 0;
+    if (t_use < 0) {
+      if (grouped) insert(1u);
+      if (groups(0)) t_use = 0;
+    }
     const uint32_t use_mask = t_use > 0 ? masks[t_use] : 0u;
     if (nslots == 0) return;
     // Long lists are split over several blocks (pieces of kFilterPiece
