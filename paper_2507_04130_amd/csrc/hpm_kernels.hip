@@ -600,19 +600,24 @@ __global__ __launch_bounds__(kBlock) void k_row_pivot(DevGraph g, const DevPlan*
 // Exclusive scan of bsum[0..nb) in place by one block; bsum[nb] = off[r] = total.
 __global__ __launch_bounds__(kBlock) void k_scan_bsum(int64_t* __restrict__ bsum, int32_t nb,
                                                       int64_t* __restrict__ off, int32_t r) {
+  // thread t owns the contiguous run [t * per, (t + 1) * per): its sum, one
+  // block scan of the sums, then the run rewritten with running prefixes
   __shared__ int64_t s_scan[kWaves + 1];
-  int64_t carry = 0;
-  for (int32_t base = 0; base < nb; base += kBlock) {
-    const int32_t i = base + threadIdx.x;
-    const int64_t x = i < nb ? bsum[i] : 0;
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan<int64_t>(x, s_scan, &tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
+  const int32_t per = (nb + kBlock - 1) / kBlock;
+  const int32_t i0 = (int32_t)threadIdx.x * per;
+  const int32_t i1 = i0 + per < nb ? i0 + per : nb;
+  int64_t sum = 0;
+  for (int32_t i = i0; i < i1; ++i) sum += bsum[i];
+  int64_t tot;
+  int64_t run = block_exclusive_scan<int64_t>(sum, s_scan, &tot);
+  for (int32_t i = i0; i < i1; ++i) {
+    const int64_t x = bsum[i];
+    bsum[i] = run;
+    run += x;
   }
   if (threadIdx.x == 0) {
-    bsum[nb] = carry;
-    off[r] = carry;
+    bsum[nb] = tot;
+    off[r] = tot;
   }
 }
 
