@@ -1285,6 +1285,7 @@ __device__ __forceinline__ uint32_t key_hash(uint64_t x) {
 }
 
 constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr int kInsertItems = 4;  // rows per thread and step of the hash insert
 
 // The value of lane - 1 (lane 0 gets its own).
 __device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long x) {
@@ -1325,35 +1326,59 @@ __global__ __launch_bounds__(kBlock) void k_filter_insert(const int32_t* __restr
                                                           unsigned long long* __restrict__ keys,
                                                           uint32_t H,
                                                           unsigned long long* __restrict__ distinct) {
+  // kInsertItems rows per thread and step (row i0 + j * kBlock + thread):
+  // their keys and first probes are loaded before any is resolved, so a
+  // thread has that many table reads in flight.
   const int lane = threadIdx.x & 63;
-  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < r; i0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t i = i0 + threadIdx.x;
-    const bool ins = i < r && off[i + 1] - off[i] >= min_len;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock * kInsertItems; i0 < r;
+       i0 += (int64_t)gridDim.x * kBlock * kInsertItems) {
+    bool ins[kInsertItems];
+#pragma unroll
+    for (int j = 0; j < kInsertItems; ++j) {
+      const int64_t i = i0 + j * kBlock + threadIdx.x;
+      ins[j] = i < r && off[i + 1] - off[i] >= min_len;
+    }
     for (int t = 0; t < 3; ++t) {
       const uint32_t m = t == 0 ? 0u : (t == 1 ? mask1 : mask2);
       if (!((tables >> t) & 1u) || (t > 0 && m == 0)) continue;  // uniform
-      bool fresh = false;
-      const unsigned long long key = ins ? row_key(rows, i, d, piv[i].x, m) : kEmptyKey;
-      // neighbouring rows often share a key: the lane before inserts it
-      const unsigned long long before = shfl_up_u64(key);
-      if (ins && !(lane > 0 && before == key)) {
-        unsigned long long* tab = keys + (size_t)t * H;
-        uint32_t h = key_hash(key) & (H - 1);
+      unsigned long long* tab = keys + (size_t)t * H;
+      unsigned long long key[kInsertItems], prev[kInsertItems];
+      uint32_t h[kInsertItems];
+      bool go[kInsertItems];
+#pragma unroll
+      for (int j = 0; j < kInsertItems; ++j) {
+        const int64_t i = i0 + j * kBlock + threadIdx.x;
+        key[j] = ins[j] ? row_key(rows, i, d, piv[i].x, m) : kEmptyKey;
+        // neighbouring rows often share a key: the lane before inserts it
+        const unsigned long long before = shfl_up_u64(key[j]);
+        go[j] = ins[j] && !(lane > 0 && before == key[j]);
+        h[j] = key_hash(key[j]) & (H - 1);
+      }
+#pragma unroll
+      for (int j = 0; j < kInsertItems; ++j) prev[j] = go[j] ? tab[h[j]] : key[j];
+      uint32_t fresh = 0;
+#pragma unroll
+      for (int j = 0; j < kInsertItems; ++j) {
+        if (!go[j]) continue;
+        uint32_t hj = h[j];
+        unsigned long long pv = prev[j];
         while (true) {  // H exceeds the number of rows, so a free slot exists
           // a slot only ever goes from empty to a key, so a plain read that
           // shows a key is final; an empty one is settled by the CAS
-          unsigned long long prev = tab[h];
-          if (prev == kEmptyKey) {
-            prev = atomicCAS(&tab[h], kEmptyKey, key);
-            if (prev == kEmptyKey) fresh = true;
+          if (pv == kEmptyKey) {
+            pv = atomicCAS(&tab[hj], kEmptyKey, key[j]);
+            if (pv == kEmptyKey) fresh |= 1u << j;
           }
-          if (prev == kEmptyKey || prev == key) break;
-          h = (h + 1) & (H - 1);
+          if (pv == kEmptyKey || pv == key[j]) break;
+          hj = (hj + 1) & (H - 1);
+          pv = tab[hj];
         }
       }
       // one atomic per wavefront for the new keys it inserted
-      const uint64_t bm = __ballot(fresh);
-      if (lane == 0 && bm) atomicAdd(&distinct[t], (unsigned long long)__popcll(bm));
+      unsigned long long n_new = 0;
+#pragma unroll
+      for (int j = 0; j < kInsertItems; ++j) n_new += __popcll(__ballot((fresh >> j) & 1u));
+      if (lane == 0 && n_new) atomicAdd(&distinct[t], n_new);
     }
   }
 }
@@ -2211,7 +2236,8 @@ hipError_t launch_filter_insert(const int32_t* rows, int32_t r, int32_t d, const
                                 uint32_t mask2, uint32_t tables, unsigned long long* keys,
                                 uint32_t H, unsigned long long* distinct, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
-  k_filter_insert<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+  k_filter_insert<<<grid_for(r, (int64_t)kBlock * kInsertItems, kMaxGridSimple), kBlock, 0,
+                    stream>>>(
       rows, r, d, piv, off, min_len, mask1, mask2, tables, keys, H, distinct);
   return hipGetLastError();
 }
