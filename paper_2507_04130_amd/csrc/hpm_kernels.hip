@@ -1392,12 +1392,36 @@ __global__ __launch_bounds__(kBlock) void k_filter_rep(const int32_t* __restrict
                                                        int32_t min_len, uint32_t rmask,
                                                        const unsigned long long* __restrict__ keys,
                                                        uint32_t H, int32_t* __restrict__ rep) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r;
-       i += (int64_t)gridDim.x * kBlock) {
-    if (off[i + 1] - off[i] < min_len) continue;
-    const unsigned long long key = row_key(rows, i, d, piv[i].x, rmask);
-    int32_t* slot = &rep[table_find(keys, H, key)];
-    if (*slot > (int32_t)i) atomicMin(slot, (int32_t)i);  // rep only decreases
+  // kInsertItems rows per thread and step, first probes loaded together
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock * kInsertItems; i0 < r;
+       i0 += (int64_t)gridDim.x * kBlock * kInsertItems) {
+    unsigned long long key[kInsertItems], seen[kInsertItems];
+    uint32_t h[kInsertItems];
+    uint32_t act = 0;
+#pragma unroll
+    for (int j = 0; j < kInsertItems; ++j) {
+      const int64_t i = i0 + j * kBlock + threadIdx.x;
+      key[j] = 0;
+      h[j] = 0;
+      if (i < r && off[i + 1] - off[i] >= min_len) {
+        act |= 1u << j;
+        key[j] = row_key(rows, i, d, piv[i].x, rmask);
+        h[j] = key_hash(key[j]) & (H - 1);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kInsertItems; ++j) seen[j] = ((act >> j) & 1u) ? keys[h[j]] : 0ull;
+#pragma unroll
+    for (int j = 0; j < kInsertItems; ++j) {
+      if (!((act >> j) & 1u)) continue;
+      while (seen[j] != key[j]) {  // the key was inserted, so the probe ends at it
+        h[j] = (h[j] + 1) & (H - 1);
+        seen[j] = keys[h[j]];
+      }
+      const int32_t i = (int32_t)(i0 + j * kBlock + threadIdx.x);
+      int32_t* slot = &rep[h[j]];
+      if (*slot > i) atomicMin(slot, i);  // rep only decreases
+    }
   }
 }
 
@@ -1424,26 +1448,36 @@ __global__ __launch_bounds__(kBlock) void k_filter_assign(DevGraph g,
   __shared__ unsigned long long s_base[2];
   for (int64_t h0 = (int64_t)blockIdx.x * kAssignTile; h0 < H;
        h0 += (int64_t)gridDim.x * kAssignTile) {
+    // the slots' dependent loads go in phases (keys, representative rows,
+    // pivots and images, list bounds), each phase's loads all in flight
     uint32_t occ = 0;
     int32_t L[kAssignItems];
+    int32_t v[kAssignItems], code[kAssignItems];
     unsigned long long lmine = 0;
 #pragma unroll
     for (int j = 0; j < kAssignItems; ++j) {
-      L[j] = 0;
       const int64_t h = h0 + j * kBlock + threadIdx.x;
       const unsigned long long key = h < H ? keys[h] : kEmptyKey;
-      if (key != kEmptyKey) {
-        int32_t v, code;
-        if (rep) {
-          const int32_t i = rep[h];
-          code = piv[i].x;
-          v = rows[(int64_t)i * d + (code >> 2)];
-        } else {
-          v = (int32_t)(key & 0xffffffffull);
-          code = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
-        }
-        L[j] = (code & 1) ? g.out_off[v + 1] - g.out_off[v] : g.in_off[v + 1] - g.in_off[v];
-        occ |= 1u << j;
+      occ |= (uint32_t)(key != kEmptyKey) << j;
+      v[j] = (int32_t)(key & 0xffffffffull);
+      code[j] = (int32_t)(((key >> 33) << 2) | ((key >> 32) & 1ull));
+    }
+    if (rep) {
+#pragma unroll
+      for (int j = 0; j < kAssignItems; ++j)
+        v[j] = ((occ >> j) & 1u) ? rep[h0 + j * kBlock + threadIdx.x] : 0;  // the row
+#pragma unroll
+      for (int j = 0; j < kAssignItems; ++j) code[j] = ((occ >> j) & 1u) ? piv[v[j]].x : 0;
+#pragma unroll
+      for (int j = 0; j < kAssignItems; ++j)
+        v[j] = ((occ >> j) & 1u) ? rows[(int64_t)v[j] * d + (code[j] >> 2)] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kAssignItems; ++j) {
+      L[j] = 0;
+      if ((occ >> j) & 1u) {
+        const int32_t* o = (code[j] & 1) ? g.out_off : g.in_off;
+        L[j] = o[v[j] + 1] - o[v[j]];
         lmine += (unsigned long long)L[j];
       }
     }
@@ -1793,31 +1827,72 @@ __global__ __launch_bounds__(kBlock) void k_filter_apply(const int32_t* __restri
                                                          const int64_t* __restrict__ slot_region,
                                                          const int32_t* __restrict__ fcount,
                                                          int64_t* __restrict__ bsum) {
+  // The items' dependent loads go in phases (lengths, keys and first probes,
+  // probe resolution, group ids, group data), so a thread has kPivotItems of
+  // each in flight.
   __shared__ int64_t s_scan[kWaves + 1];
+  int64_t L[kPivotItems];
+  int2 pv[kPivotItems];
+  unsigned long long key[kPivotItems], seen[kPivotItems];
+  uint32_t h[kPivotItems];
+  uint32_t grp = 0;  // bit it: item it has a row whose list is long enough
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+    L[it] = i < r ? off[i + 1] - off[i] : 0;
+    if (i < r && L[it] >= min_len) grp |= 1u << it;
+  }
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+    key[it] = 0;
+    h[it] = 0;
+    if ((grp >> it) & 1u) {
+      pv[it] = piv[i];
+      key[it] = row_key(rows, i, d, pv[it].x, rmask);
+      h[it] = key_hash(key[it]) & (H - 1);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) seen[it] = ((grp >> it) & 1u) ? keys[h[it]] : 0ull;
+  int32_t sidx[kPivotItems];
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) {
+    if (!((grp >> it) & 1u)) continue;
+    // the key was inserted, so the probe ends at it
+    while (seen[it] != key[it]) {
+      h[it] = (h[it] + 1) & (H - 1);
+      seen[it] = keys[h[it]];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kPivotItems; ++it) sidx[it] = ((grp >> it) & 1u) ? dense[h[it]] : 0;
+  uint32_t same = grp;
+  if (rmask != 0) {
+    int64_t rep[kPivotItems];
+#pragma unroll
+    for (int it = 0; it < kPivotItems; ++it) rep[it] = ((grp >> it) & 1u) ? slot_rep[sidx[it]] : 0;
+#pragma unroll
+    for (int it = 0; it < kPivotItems; ++it) {
+      if (!((grp >> it) & 1u)) continue;
+      const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
+      bool eq = true;
+      for (int q = 0; q < d; ++q)
+        if ((rmask >> q) & 1u) eq = eq && rows[i * d + q] == rows[rep[it] * d + q];
+      if (!eq) same &= ~(1u << it);
+    }
+  }
   int64_t sum = 0;
 #pragma unroll
   for (int it = 0; it < kPivotItems; ++it) {
     const int64_t i = (int64_t)blockIdx.x * kPivotTile + it * kBlock + threadIdx.x;
-    if (i < r) {
-      int64_t L = off[i + 1] - off[i];
-      if (L >= min_len) {
-        const int2 pv = piv[i];
-        const unsigned long long key = row_key(rows, i, d, pv.x, rmask);
-        const int32_t sidx = dense[table_find(keys, H, key)];
-        bool same = true;
-        if (rmask != 0) {
-          const int64_t j = slot_rep[sidx];
-          for (int q = 0; q < d; ++q)
-            if ((rmask >> q) & 1u) same = same && rows[i * d + q] == rows[j * d + q];
-        }
-        if (same) {
-          piv[i] = make_int2(pv.x | 2, (int32_t)slot_region[sidx]);
-          L = fcount[sidx];
-        }
-      }
-      len[i] = L;
-      sum += L;
+    if (i >= r) continue;
+    if ((same >> it) & 1u) {
+      piv[i] = make_int2(pv[it].x | 2, (int32_t)slot_region[sidx[it]]);
+      L[it] = fcount[sidx[it]];
     }
+    len[i] = L[it];
+    sum += L[it];
   }
   const int64_t tot = block_sum<int64_t>(sum, s_scan);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -2250,7 +2325,7 @@ hipError_t launch_filter_groups(const DevGraph& g, const int32_t* rows, int32_t 
                                 unsigned long long* counters, hipStream_t stream) {
   if (r <= 0) return hipSuccess;
   if (rmask) {
-    k_filter_rep<<<grid_for(r, kBlock, kMaxGridSimple), kBlock, 0, stream>>>(
+    k_filter_rep<<<grid_for(r, (int64_t)kBlock * kInsertItems, kMaxGridSimple), kBlock, 0, stream>>>(
         rows, r, d, piv, off, min_len, rmask, keys, H, rep);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
