@@ -199,6 +199,27 @@ def test_reorder_and_budget_invariance():
         say(f"budget {p.name}/{mode}: chunks={st['chunks']} count={c2}")
 
 
+def test_whole_depth_piece_and_its_chunked_retry():
+    # A depth with millions of candidates and rows of over 512 is expanded
+    # whole, into room for one frontier chunk of new rows; under tight budgets
+    # more rows pass than fit, and the depth is redone in chunks of
+    # candidates.  Counts and rows equal the oracle's whatever the budget.
+    g = rmat(12, 1 << 17, seed=31)
+    dg = hpm.Graph.from_host(g)
+    for name in ("cycle4", "clique4_minus1"):
+        p = motif(name)
+        want = oracle.match(g, p, ISO, threads=8)
+        for budget in (None, 16 << 20, 4 << 20):
+            cnt, rows = gpu_rows(dg, p, ISO, budget=budget)
+            st = hpm.last_stats()
+            say(f"whole depth {name} budget={budget}: count={cnt} rows={st['rows'][:4]} "
+                f"work={st['work'][:4]} chunks={st['chunks']}")
+            assert cnt == want.count, (name, budget)
+            np.testing.assert_array_equal(rows, want.rows, err_msg=f"{name} {budget}")
+            c2, _ = hpm.match(dg, p, ISO, budget=budget)
+            assert c2 == want.count, (name, budget)
+
+
 def test_relabelled_target():
     g = configs.c2_graph(scale=11)
     perm = np.random.default_rng(9).permutation(g.n)
