@@ -1032,6 +1032,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   }
 }
 
+constexpr int kCountBatch = 4;  // candidates of an unfiltered row checked together (count pass)
+
 // Last level, count only, after a filter that enforced every condition
 // between the new position and the mapped positions it is tied to by a
 // pattern arc.  What a filtered row still has to check is injectivity and,
@@ -1108,41 +1110,91 @@ __global__ __launch_bounds__(kBlock) void k_count_rows(DevGraph g, const DevPlan
           }
         }
       } else if (len > 0) {
+        // Four candidates at a time: their ids, flags and pivot-arc columns
+        // are loaded together, and each relation's binary searches (one list,
+        // four keys) advance in step, so the lane keeps four loads in flight.
         const int32_t b = pv.x >> 2;
         const bool via_out = (pv.x & 1) != 0;
-        for (int32_t j = 0; j < len; ++j) {
-          const int32_t pos = pv.y + j;
-          const int32_t c = via_out ? g.out_nbrs[pos] : g.in_nbrs[pos];
-          bool ok = ((abits[c >> 5] >> (c & 31)) & 1u) != 0;
-          if (ok) {
-            if (via_out) {
-              if (P->amask[b][a]) ok = arc_ok(g, P, b, a, pos);
-            } else if (P->amask[a][b]) {
-              ok = arc_ok_in(g, P, a, b, pos);
-            }
+        const int32_t* __restrict__ plist = via_out ? g.out_nbrs : g.in_nbrs;
+        for (int32_t j0 = 0; j0 < len; j0 += kCountBatch) {
+          int32_t c[kCountBatch];
+          uint32_t ok = 0;
+#pragma unroll
+          for (int j = 0; j < kCountBatch; ++j) {
+            c[j] = j0 + j < len ? plist[pv.y + j0 + j] : 0;
+            ok |= (uint32_t)(j0 + j < len) << j;
           }
-          for (int q = 0; q < d && ok; ++q) ok = row[q] != c;
+          uint32_t w[kCountBatch];
+#pragma unroll
+          for (int j = 0; j < kCountBatch; ++j) w[j] = ((ok >> j) & 1u) ? abits[c[j] >> 5] : 0u;
+#pragma unroll
+          for (int j = 0; j < kCountBatch; ++j) {
+            if (!((ok >> j) & 1u)) continue;
+            bool okj = ((w[j] >> (c[j] & 31)) & 1u) != 0;
+            const int32_t pos = pv.y + j0 + j;
+            if (okj) {
+              if (via_out) {
+                if (P->amask[b][a]) okj = arc_ok(g, P, b, a, pos);
+              } else if (P->amask[a][b]) {
+                okj = arc_ok_in(g, P, a, b, pos);
+              }
+            }
+            for (int q = 0; q < d && okj; ++q) okj = row[q] != c[j];
+            if (!okj) ok &= ~(1u << j);
+          }
           for (int q = 0; q < d && ok; ++q) {
             const int32_t fq = row[q];
-            if ((fw >> q) & 1u) {
-              if (!(q == b && via_out)) {
-                const int32_t e = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c);
-                ok = e >= 0 && arc_ok(g, P, q, a, e);
+            for (int dir = 0; dir < 2 && ok; ++dir) {
+              // dir 0: pattern arc q -> a <=> target arc f(q) -> c, in out(f(q));
+              // dir 1: pattern arc a -> q <=> target arc c -> f(q), in in(f(q))
+              const bool req = dir ? ((bw >> q) & 1u) != 0 : ((fw >> q) & 1u) != 0;
+              if (req ? (q == b && via_out == (dir == 0)) : !iso) continue;
+              const int32_t* __restrict__ cl = dir ? g.in_nbrs : g.out_nbrs;
+              const int32_t lo = dir ? g.in_off[fq] : g.out_off[fq];
+              const int32_t hi = dir ? g.in_off[fq + 1] : g.out_off[fq + 1];
+              int32_t l[kCountBatch], h[kCountBatch];
+#pragma unroll
+              for (int j = 0; j < kCountBatch; ++j) {
+                l[j] = lo;
+                h[j] = ((ok >> j) & 1u) ? hi : lo;
               }
-            } else if (iso) {
-              ok = find_in(g.out_nbrs, g.out_off[fq], g.out_off[fq + 1], c) < 0;
-            }
-            if (!ok) break;
-            if ((bw >> q) & 1u) {
-              if (!(q == b && !via_out)) {
-                const int32_t e = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c);
-                ok = e >= 0 && arc_ok_in(g, P, a, q, e);
+              for (;;) {
+                int32_t mid[kCountBatch], v[kCountBatch];
+                uint32_t go = 0;
+#pragma unroll
+                for (int j = 0; j < kCountBatch; ++j) {
+                  const bool gj = l[j] < h[j];
+                  mid[j] = gj ? l[j] + ((h[j] - l[j]) >> 1) : 0;
+                  go |= (uint32_t)gj << j;
+                }
+                if (!go) break;
+#pragma unroll
+                for (int j = 0; j < kCountBatch; ++j) v[j] = ((go >> j) & 1u) ? cl[mid[j]] : 0;
+#pragma unroll
+                for (int j = 0; j < kCountBatch; ++j) {
+                  if (!((go >> j) & 1u)) continue;
+                  if (v[j] < c[j])
+                    l[j] = mid[j] + 1;
+                  else
+                    h[j] = mid[j];
+                }
               }
-            } else if (iso) {
-              ok = find_in(g.in_nbrs, g.in_off[fq], g.in_off[fq + 1], c) < 0;
+#pragma unroll
+              for (int j = 0; j < kCountBatch; ++j) {
+                if (!((ok >> j) & 1u)) continue;
+                const bool found = l[j] < hi && cl[l[j]] == c[j];
+                bool okj;
+                if (!req)
+                  okj = !found;
+                else if (dir == 0)
+                  okj = found && arc_ok(g, P, q, a, l[j]);
+                else
+                  okj = found && arc_ok_in(g, P, a, q, l[j]);
+                if (!okj) ok &= ~(1u << j);
+              }
             }
           }
-          acc += ok ? 1 : 0;
+          acc += __popc(ok);
         }
       }
       if (rest) rest[i] = left;
