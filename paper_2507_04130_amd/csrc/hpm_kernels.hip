@@ -1641,16 +1641,50 @@ __device__ __forceinline__ uint32_t filter_check(const DevGraph& g, const DevPla
     wave_sync();
   }
   const bool need = req && (in_dir ? P->amask[a][q] : P->amask[q][a]) != 0;
+  int32_t at[kFilterWaveItems];
+  if (staged) {
+#pragma unroll
+    for (int it = 0; it < kFilterWaveItems; ++it) {
+      const int32_t x = ((keep >> it) & 1u) ? lds_find(wl, len, c[it]) : -1;
+      at[it] = x >= 0 ? lo + x : -1;
+    }
+  } else {
+    // the items' searches of the one cut list advance in step
+    int32_t l[kFilterWaveItems], h[kFilterWaveItems];
+#pragma unroll
+    for (int it = 0; it < kFilterWaveItems; ++it) {
+      l[it] = lo;
+      h[it] = ((keep >> it) & 1u) ? hi : lo;
+    }
+    for (;;) {
+      int32_t mid[kFilterWaveItems], v[kFilterWaveItems];
+      uint32_t go = 0;
+#pragma unroll
+      for (int it = 0; it < kFilterWaveItems; ++it) {
+        const bool gi = l[it] < h[it];
+        mid[it] = gi ? l[it] + ((h[it] - l[it]) >> 1) : 0;
+        go |= (uint32_t)gi << it;
+      }
+      if (!go) break;
+#pragma unroll
+      for (int it = 0; it < kFilterWaveItems; ++it) v[it] = ((go >> it) & 1u) ? cl[mid[it]] : 0;
+#pragma unroll
+      for (int it = 0; it < kFilterWaveItems; ++it) {
+        if (!((go >> it) & 1u)) continue;
+        if (v[it] < c[it])
+          l[it] = mid[it] + 1;
+        else
+          h[it] = mid[it];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kFilterWaveItems; ++it)
+      at[it] = ((keep >> it) & 1u) && l[it] < hi && cl[l[it]] == c[it] ? l[it] : -1;
+  }
 #pragma unroll
   for (int it = 0; it < kFilterWaveItems; ++it) {
     if (!((keep >> it) & 1u)) continue;
-    int32_t pos;
-    if (staged) {
-      const int32_t x = lds_find(wl, len, c[it]);
-      pos = x >= 0 ? lo + x : -1;
-    } else {
-      pos = find_in(cl, lo, hi, c[it]);
-    }
+    const int32_t pos = at[it];
     bool ok;
     if (!req)
       ok = pos < 0;
